@@ -1,0 +1,552 @@
+// k_common.hip -- format-independent ROR-BK kernels: partition, sampler,
+// norms, residual-driven selection (per-block norms, stop test, top-K) and the
+// greedy block's Cholesky solve.
+#include "rorbk_device.h"
+
+namespace rorbk {
+
+// ------------------------------------------------------------- partition --
+// Algorithm 1, first step: k contiguous blocks of floor(m/k) rows, the first
+// (m mod k) of them one row longer.  hoff[t] = sum_{s<t} b_s^2 locates the
+// stored inverse of block t.
+__global__ void k_partition(int64_t m, int64_t k, int64_t *off, int64_t *hoff) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > k) return;
+    const int64_t q = m / k, rem = m - k * q;
+    off[t] = t * q + (t < rem ? t : rem);
+    const int64_t big = (t < rem ? t : rem);
+    hoff[t] = big * (q + 1) * (q + 1) + (t - big) * q * q;
+}
+
+hipError_t launch_partition(int64_t m, int64_t k, int64_t *off, int64_t *hoff,
+                            hipStream_t s) {
+    const int64_t nb = (k + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_partition, dim3((unsigned)nb), dim3(256), 0, s, m, k, off, hoff);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- sampler --
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), counter form: word c of a
+// seed is the generator's output finaliser applied to seed + (c+1)*0x9E37..15.
+__device__ __forceinline__ uint64_t splitmix_word(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+// Draw l of outer iteration j (Algorithm 1, inner loop; proposal of Section 2):
+// u = top 53 bits of word 3j + l - 1 scaled to [0,1); the block is the number
+// of running sums W_t not exceeding u * W_{k-1} (inverse CDF of
+// P = Pbar / sum Pbar), at most k - 1.
+__global__ void k_sample(uint64_t seed, int64_t j0, int64_t count, const double *__restrict__ W,
+                         int64_t k, int32_t *__restrict__ tau) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= 3 * count) return;
+    const int64_t it = d / 3;
+    const int l = (int)(d - 3 * it);
+    const uint64_t w = splitmix_word(seed, (uint64_t)(3 * (j0 + it) + l));
+    const double u = (double)(w >> 11) * 0x1.0p-53;
+    const double target = u * W[k - 1];
+    // W is non-decreasing: count of W_t <= target by binary search
+    int64_t lo = 0, hi = k;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (W[mid] <= target) lo = mid + 1; else hi = mid;
+    }
+    tau[d] = (int32_t)(lo > k - 1 ? k - 1 : lo);
+}
+
+hipError_t launch_sample(uint64_t seed, int64_t j0, int64_t count, const double *W,
+                         int64_t k, int32_t *tau, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t nb = (3 * count + 255) / 256;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)nb), dim3(256), 0, s, seed, j0, count, W, k, tau);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_i32(const int32_t *src, int32_t *dst, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i];
+}
+
+hipError_t launch_copy_tau(const int32_t *src, int32_t *dst, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       src, dst, count);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- norms --
+// ||v||^2 in a fixed order: one workgroup, contiguous thread ranges, then
+// the workgroup sum.
+template <typename V>
+__global__ __launch_bounds__(1024) void k_norm2(const V *__restrict__ v, int64_t len,
+                                                double *__restrict__ out) {
+    __shared__ double sh[16];
+    const int64_t per = (len + blockDim.x - 1) / blockDim.x;
+    const int64_t a = threadIdx.x * per, e = (a + per < len) ? a + per : len;
+    double s = 0.0;
+    for (int64_t i = a; i < e; ++i) {
+        const double t = (double)v[i];
+        s = __builtin_fma(t, t, s);
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s;
+}
+
+hipError_t launch_norm2(const void *v, int vec, int64_t len, double *red, double *out,
+                        hipStream_t s) {
+    (void)red;
+    if (vec == VEC_F64)
+        hipLaunchKernelGGL(k_norm2<double>, dim3(1), dim3(1024), 0, s, (const double *)v, len, out);
+    else
+        hipLaunchKernelGGL(k_norm2<float>, dim3(1), dim3(1024), 0, s, (const float *)v, len, out);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- selection --
+// Keys order |r_i|: the IEEE bits of |r_i| (sign cleared) are monotone in
+// |r_i| and hence in r_i^2 (Algorithm 1, greedy step), without rounding a
+// square.  Ties go to the lower index.
+__device__ __forceinline__ uint64_t key_of(double v) {
+    return (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffULL;
+}
+__device__ __forceinline__ uint64_t key_of(float v) {
+    return (uint64_t)(__float_as_uint(v) & 0x7fffffffu);
+}
+
+constexpr int SEL_T = 256;          // threads of the selection kernels
+constexpr int SEL_CHUNK = 4096;     // rows per selection chunk (upper bound)
+constexpr int SEL_MERGE = 8192;     // candidates per merge workgroup
+constexpr int SEL_BPC = 256;        // blocks per selection chunk (upper bound)
+
+// Exclusive scan of one 64-bit value per thread over the workgroup.
+__device__ __forceinline__ uint64_t block_exscan_u64(uint64_t v, uint64_t *sh, uint64_t *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) base += sh[i];
+        tot += sh[i];
+    }
+    *total = tot;
+    __syncthreads();
+    return base + inc - v;
+}
+
+// Radix select over keys[0..N) in LDS: finds the K-th largest key T and the
+// number `need` of elements equal to T that complete the top K.
+__device__ void radix_select(const uint64_t *keys, int N, int K, int nbits,
+                             uint64_t *T_out, int *need_out) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int s_need;
+    if (threadIdx.x == 0) { s_prefix = 0; s_mask = 0; s_need = K; }
+    __syncthreads();
+    for (int shift = nbits - 8; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        const uint64_t prefix = s_prefix, mask = s_mask;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const uint64_t kk = keys[i];
+            if (((kk ^ prefix) & mask) == 0) atomicAdd(&hist[(kk >> shift) & 255], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            uint32_t h[4];
+            uint32_t ls = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { h[u] = hist[4 * lane + u]; ls += h[u]; }
+            // inclusive suffix sums over lanes (higher bins first)
+            uint32_t suf = ls;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t t = __shfl_down(suf, off, 64);
+                if (lane + off < 64) suf += t;
+            }
+            const int need = s_need;
+            const unsigned long long bal = __ballot(suf >= (uint32_t)need);
+            const int top = 63 - __clzll(bal);   // the highest lane reaching `need`
+            if (lane == top) {
+                uint32_t above = suf - ls;
+                int bin = 4 * lane;
+                for (int u = 3; u >= 0; --u) {
+                    if (above + h[u] >= (uint32_t)need) { bin = 4 * lane + u; break; }
+                    above += h[u];
+                }
+                s_need = need - (int)above;
+                s_prefix = prefix | ((uint64_t)bin << shift);
+                s_mask = mask | ((uint64_t)255 << shift);
+            }
+        }
+        __syncthreads();
+    }
+    *T_out = s_prefix;
+    *need_out = s_need;
+    __syncthreads();
+}
+
+// Emit, in ascending index order, every element with key > T and the first
+// `need` elements with key == T.  keys/ids in LDS (ids == NULL: position).
+__device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, int K, uint64_t T,
+                             int need, uint64_t *okey, int32_t *oidx, int32_t base) {
+    __shared__ uint64_t sh[16];
+    const int per = (N + blockDim.x - 1) / blockDim.x;
+    const int a = threadIdx.x * per, e = (a + per < N) ? a + per : N;
+    uint32_t gt = 0, eq = 0;
+    for (int i = a; i < e; ++i) {
+        gt += keys[i] > T;
+        eq += keys[i] == T;
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exscan_u64(((uint64_t)gt << 32) | eq, sh, &tot);
+    uint32_t g = (uint32_t)(ex >> 32), q = (uint32_t)(ex & 0xffffffffu);
+    for (int i = a; i < e; ++i) {
+        const uint64_t kk = keys[i];
+        int pos = -1;
+        if (kk > T) {
+            pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
+            ++g;
+        } else if (kk == T) {
+            if (q < (uint32_t)need) pos = (int)(g + q);
+            ++q;
+        }
+        if (pos >= 0 && pos < K) {
+            okey[pos] = kk;
+            oidx[pos] = (ids ? ids[i] : i) + base;
+        }
+    }
+}
+
+// Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
+// (Algorithm 1, the full residual), per-block ||r_t||^2, the chunk's ||r||^2,
+// and the chunk's local top-K candidates (keys, global row indices).
+template <typename V>
+__global__ __launch_bounds__(SEL_T) void k_select_chunk(
+    const V *__restrict__ b, const double *__restrict__ axp, int nseg, int64_t m,
+    const int64_t *__restrict__ off, int64_t k, int64_t bpc, int K, V *__restrict__ r,
+    double *__restrict__ bn, double *__restrict__ cn, uint64_t *__restrict__ ckey,
+    int32_t *__restrict__ cidx, int do_topk, const Ctrl *__restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    __shared__ uint64_t keys[SEL_CHUNK];
+    __shared__ double vals[SEL_CHUNK];
+    __shared__ double s_bn[SEL_BPC];
+    const int64_t t0 = (int64_t)blockIdx.x * bpc;
+    const int64_t t1 = (t0 + bpc < k) ? t0 + bpc : k;
+    const int64_t r0 = off[t0], r1 = off[t1];
+    const int N = (int)(r1 - r0);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int64_t row = r0 + i;
+        V s = (V)0;
+        if (axp) {
+            double a = 0.0;
+            for (int sg = 0; sg < nseg; ++sg) a += axp[(int64_t)sg * m + row];
+            s = (V)((double)b[row] - a);
+        } else {
+            s = b[row];
+        }
+        r[row] = s;
+        vals[i] = (double)s;
+        keys[i] = key_of(s);
+    }
+    __syncthreads();
+    // per-block squared norms: one wave per block, lanes stride the rows
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t t = t0 + w; t < t1; t += nw) {
+        double s = 0.0;
+        for (int64_t i = off[t] + lane; i < off[t + 1]; i += 64) {
+            const double v = vals[i - r0];
+            s = __builtin_fma(v, v, s);
+        }
+        s = group_sum(s, 64);
+        if (lane == 0) { bn[t] = s; s_bn[t - t0] = s; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int64_t t = t0; t < t1; ++t) s += s_bn[t - t0];
+        cn[blockIdx.x] = s;
+    }
+    if (!do_topk) return;
+    uint64_t T;
+    int need;
+    radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &need);
+    compact_topk(keys, nullptr, N, K, T, need, ckey + (int64_t)blockIdx.x * K,
+                 cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
+}
+
+// Merge groups of candidate lists (each K long, ascending rows) into K
+// candidates per group.  The last level (one group) finishes the iteration:
+// RRN from the chunk norms in chunk order, the stop test, the greedy set I
+// (or the replayed one) with r_I, and the records.
+template <typename V>
+__global__ __launch_bounds__(SEL_T) void k_select_merge(
+    const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx, int nlists,
+    int lists_per_group, int K, uint64_t *__restrict__ okey, int32_t *__restrict__ oidx,
+    int final_level, const double *__restrict__ cn, int ncn, const V *__restrict__ r,
+    Ctrl *__restrict__ ctrl, int stop_test, int do_topk, int64_t it, double *rec_rrn,
+    int32_t *rec_I, const int32_t *replay_I, int32_t *I_out, double *rI_out) {
+    if (ctrl->done) return;
+    __shared__ uint64_t keys[SEL_MERGE];
+    __shared__ int32_t ids[SEL_MERGE];
+    __shared__ int s_stop;
+    const int l0 = blockIdx.x * lists_per_group;
+    const int l1 = (l0 + lists_per_group < nlists) ? l0 + lists_per_group : nlists;
+    const int N = (l1 - l0) * K;
+    if (do_topk) {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            keys[i] = ckey[(int64_t)l0 * K + i];
+            ids[i] = cidx[(int64_t)l0 * K + i];
+        }
+        __syncthreads();
+        uint64_t T;
+        int need;
+        radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &need);
+        if (!final_level) {
+            compact_topk(keys, ids, N, K, T, need, okey + (int64_t)blockIdx.x * K,
+                         oidx + (int64_t)blockIdx.x * K, 0);
+            return;
+        }
+        __shared__ uint64_t fk[MAXB];
+        __shared__ int32_t fi[MAXB];
+        compact_topk(keys, ids, N, K, T, need, fk, fi, 0);
+        __syncthreads();
+        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rn2 = 0.0;
+        for (int c = 0; c < ncn; ++c) rn2 += cn[c];
+        const double rn = sqrt(rn2);
+        ctrl->rnorm2 = rn2;
+        ctrl->last_it = it;
+        const double bn2 = ctrl->bnorm2;
+        const double rrn = (bn2 > 0.0) ? rn / sqrt(bn2) : 0.0;
+        if (rec_rrn) rec_rrn[it] = rrn;
+        int stop = 0;
+        if (!isfinite(rn2)) {
+            ctrl->status = RORBK_ERR_NONFINITE;
+            stop = 1;
+        } else if (stop_test && rn < ctrl->thr) {
+            stop = 1;
+        }
+        if (stop) {
+            ctrl->done = 1;
+            ctrl->conv_it = it;
+        }
+        s_stop = stop;
+    }
+    __syncthreads();
+    if (s_stop || !I_out) return;
+    for (int p = threadIdx.x; p < K; p += blockDim.x) {
+        const int32_t row = replay_I ? replay_I[it * K + p] : ids[p];
+        I_out[p] = row;
+        rI_out[p] = (double)r[row];
+        if (rec_I) rec_I[it * K + p] = row;
+    }
+}
+
+hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream_t s) {
+    const Layout &L = h->L;
+    const int K = (int)L.K;
+    const int do_topk = (!a.skip_topk && !a.replay_I) ? 1 : 0;
+    if (a.vec == VEC_F64)
+        hipLaunchKernelGGL(k_select_chunk<double>, dim3(L.nch_s), dim3(SEL_T), 0, s,
+                           (const double *)a.b, a.axp, a.nseg, L.m, h->d_off, L.k, L.bpc, K,
+                           (double *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
+                           h->d_ctrl);
+    else
+        hipLaunchKernelGGL(k_select_chunk<float>, dim3(L.nch_s), dim3(SEL_T), 0, s,
+                           (const float *)a.b, a.axp, a.nseg, L.m, h->d_off, L.k, L.bpc, K,
+                           (float *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
+                           h->d_ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // merge levels: lists of K candidates, at most SEL_MERGE per workgroup
+    int nlists = L.nch_s;
+    const int per = SEL_MERGE / K;
+    const uint64_t *ik = h->d_ckey;
+    const int32_t *ii = h->d_cidx;
+    int flip = 0;
+    while (do_topk && nlists > per) {
+        const int groups = (nlists + per - 1) / per;
+        uint64_t *ok = flip ? h->d_ckey : h->d_ckey2;
+        int32_t *oi = flip ? h->d_cidx : h->d_cidx2;
+        if (a.vec == VEC_F64)
+            hipLaunchKernelGGL(k_select_merge<double>, dim3(groups), dim3(SEL_T), 0, s, ik, ii,
+                               nlists, per, K, ok, oi, 0, nullptr, 0, (const double *)nullptr,
+                               h->d_ctrl, 0, 1, a.it, nullptr, nullptr, nullptr, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL(k_select_merge<float>, dim3(groups), dim3(SEL_T), 0, s, ik, ii,
+                               nlists, per, K, ok, oi, 0, nullptr, 0, (const float *)nullptr,
+                               h->d_ctrl, 0, 1, a.it, nullptr, nullptr, nullptr, nullptr, nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        ik = ok;
+        ii = oi;
+        nlists = groups;
+        flip ^= 1;
+    }
+    if (a.vec == VEC_F64)
+        hipLaunchKernelGGL(k_select_merge<double>, dim3(1), dim3(SEL_T), 0, s, ik, ii, nlists,
+                           nlists, K, nullptr, nullptr, 1, h->d_cn, L.nch_s, (const double *)a.r,
+                           h->d_ctrl, a.stop_test, do_topk, a.it,
+                           a.record_rrn ? a.rec_rrn : nullptr, a.record_I ? a.rec_I : nullptr,
+                           a.replay_I, a.I_out, a.rI_out);
+    else
+        hipLaunchKernelGGL(k_select_merge<float>, dim3(1), dim3(SEL_T), 0, s, ik, ii, nlists,
+                           nlists, K, nullptr, nullptr, 1, h->d_cn, L.nch_s, (const float *)a.r,
+                           h->d_ctrl, a.stop_test, do_topk, a.it,
+                           a.record_rrn ? a.rec_rrn : nullptr, a.record_I ? a.rec_I : nullptr,
+                           a.replay_I, a.I_out, a.rI_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ greedy block solve --
+// (A_I A_I^T + lambda I) y = rhs, the greedy step of Algorithm 1: the Gram
+// partials of the column chunks are summed in chunk order, lambda is added to
+// the diagonal, the packed FP64 Cholesky factor is formed in LDS and the two
+// triangular solves run on one wave.  rhs = r_I (forward) or, for the adjoint,
+// -(sum of the partial products A_I g).
+__global__ __launch_bounds__(256) void k_chol_solve(const double *__restrict__ Gpart, int nch,
+                                                    int K, double lambda,
+                                                    const double *__restrict__ rI,
+                                                    const double *__restrict__ Pin, int nchP,
+                                                    int bmax, double *__restrict__ y,
+                                                    Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double Lp[PACKED_MAX];
+    __shared__ double rhs[MAXB];
+    const int tot = K * (K + 1) / 2;
+    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
+        int i = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
+        while (i * (i + 1) / 2 > f) --i;
+        while ((i + 1) * (i + 2) / 2 <= f) ++i;
+        const int j = f - i * (i + 1) / 2;
+        double g = 0.0;
+        for (int c = 0; c < nch; ++c) g += Gpart[(int64_t)c * K * K + i * K + j];
+        if (i == j) g += lambda;
+        Lp[f] = g;
+    }
+    for (int p = threadIdx.x; p < K; p += blockDim.x) {
+        if (rI) {
+            rhs[p] = rI[p];
+        } else {
+            double s = 0.0;
+            for (int c = 0; c < nchP; ++c) s += Pin[(int64_t)c * bmax + p];
+            rhs[p] = -s;
+        }
+    }
+    __syncthreads();
+    if (!chol_packed(Lp, K)) {
+        if (threadIdx.x == 0) {
+            ctrl->status = RORBK_ERR_NOT_SPD;
+            ctrl->done = 1;
+        }
+        return;
+    }
+    chol_solve_wave(Lp, K, rhs, rhs);
+    __syncthreads();
+    for (int p = threadIdx.x; p < K; p += blockDim.x) y[p] = rhs[p];
+}
+
+hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
+                             const double *rI, const double *Pin, double *y, hipStream_t s) {
+    const Layout &L = h->L;
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K, h->lambda, rI,
+                       Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- refinement glue --
+__global__ void k_cast_f64_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_axpy_f32_f64(const float *__restrict__ d, double *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += (double)d[i];
+}
+__global__ void k_zero(uint32_t *p, int64_t words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+hipError_t launch_cast_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_f64_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src,
+                       dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_f32_to_f64(const float *d, double *x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_f32_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, x,
+                       n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s) {
+    const int64_t words = bytes / 4;
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+// Inner stop threshold of a refinement step: the inner residual estimates
+// b - A(x + d); stop once it is below max(eta ||r_out||, tol ||b||).  The
+// recorded RRN stays relative to the original ||b||.
+__global__ void k_refine_ctrl(Ctrl *c, double tol, double eta, const double *__restrict__ rout2,
+                              double bnorm2) {
+    c->done = 0;
+    c->status = 0;
+    c->bnorm2 = bnorm2;
+    const double a = eta * sqrt(*rout2), bb = tol * sqrt(bnorm2);
+    c->thr = a > bb ? a : bb;
+}
+
+__global__ void k_init_ctrl(Ctrl *c, double tol, const double *__restrict__ bnorm2) {
+    c->done = 0;
+    c->status = 0;
+    c->conv_it = -1;
+    c->bnorm2 = *bnorm2;
+    c->thr = tol * sqrt(*bnorm2);
+    c->rnorm2 = 0.0;
+    c->last_it = -1;
+}
+
+hipError_t launch_init_ctrl(Ctrl *c, double tol, const double *bnorm2, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(1), 0, s, c, tol, bnorm2);
+    return hipGetLastError();
+}
+
+__global__ void k_set_thr(Ctrl *c, double thr) { c->thr = thr; }
+
+hipError_t launch_set_thr(Ctrl *c, double thr, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_thr, dim3(1), dim3(1), 0, s, c, thr);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy_f64(const double *__restrict__ d, double *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += d[i];
+}
+
+hipError_t launch_axpy_f64(const double *d, double *x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_refine_ctrl(Ctrl *c, double tol, double eta, const double *rout2,
+                                  double outer_bnorm2, hipStream_t s) {
+    hipLaunchKernelGGL(k_refine_ctrl, dim3(1), dim3(1), 0, s, c, tol, eta, rout2, outer_bnorm2);
+    return hipGetLastError();
+}
+
+}  // namespace rorbk

@@ -1,0 +1,233 @@
+// rorbk_internal.h -- handle layout and kernel launchers of the MI355X ROR-BK
+// library.  Internal to the library; the public ABI is include/rorbk.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rorbk.h"
+
+namespace rorbk {
+
+// Device-resident control block.  Written only by the single-workgroup
+// selection and solve kernels; every iteration kernel reads `done` first and
+// returns at once when it is set (the stop test, Algorithm 1, ends the solve
+// before the greedy step).
+struct Ctrl {
+    int32_t done;        // 1 once converged or failed
+    int32_t status;      // RORBK_OK, RORBK_ERR_NONFINITE or RORBK_ERR_NOT_SPD
+    int64_t conv_it;     // iteration index (from the solve's start) that stopped
+    double bnorm2;       // ||b||^2 of the current right-hand side
+    double thr;          // stop when ||r|| < thr (tol * ||b||)
+    double rnorm2;       // last measured ||r||^2
+    int64_t last_it;     // last iteration whose residual was measured
+    double pad[2];
+};
+
+// Vector-type tag: double (FP64 solve) or float (FP32/BF16 storage solve).
+enum VecType { VEC_F64 = 0, VEC_F32 = 1 };
+
+// Row set of one block step: a fixed block (its index read on the device from
+// tau[tau_index]) or a gathered set of `count` rows at `idx`.
+struct RowSel {
+    int32_t kind;         // 0 fixed block via tau, 1 gathered, -1 none
+    int32_t count;        // gathered: number of rows
+    int64_t tau_index;    // fixed: index into the tau array
+    const int32_t *idx;   // gathered: row indices (device)
+};
+
+struct Layout {
+    int64_t m, n, ld, nnz;
+    int32_t format, dtype;
+    int64_t k, q, rem, K, bmax;
+    // update kernel column chunks
+    int64_t wu;           // columns per update workgroup (multiple of 128)
+    int32_t nch_u;        // update chunks
+    // greedy Gram column chunks
+    int64_t wg;           // columns per Gram workgroup
+    int32_t nch_g;
+    // residual segments (2048 columns each)
+    int32_t nseg;
+    // selection chunks (whole blocks)
+    int64_t bpc;          // blocks per selection chunk
+    int32_t nch_s;        // selection chunks
+    int32_t pad_;
+};
+
+}  // namespace rorbk
+
+struct rorbk_handle_s {
+    rorbk::Layout L;
+    hipStream_t stream;
+    double lambda;
+    int32_t aligned;          // 16-byte vector loads allowed on the matrix
+    int32_t aligned64;        // same for the FP64 master copy
+    const void *A;            // working matrix values (non-owning)
+    const double *A64;        // FP64 master (non-owning, may be NULL)
+    const int64_t *rowptr;    // CSR (non-owning)
+    const int32_t *colidx;
+
+    // setup results (owned)
+    int64_t *d_off;           // k+1
+    double *d_S, *d_pbar, *d_W;
+    int64_t *d_hoff;          // k+1 offsets into d_H
+    double *d_H;              // stored block inverses
+    // CSR: transposed layout of each fixed block for A_t^T y
+    int64_t *d_tptr;          // per block: offset of its column list (k+1)
+    int32_t *d_tcol;          // unique columns of each block, ascending
+    int64_t *d_tseg;          // per unique column: start in d_trow/d_tval (+1 sentinel per block)
+    int32_t *d_trow;          // local row index of each entry
+    int64_t tcols_total;
+
+    // per-solve workspaces (owned)
+    rorbk::Ctrl *d_ctrl;
+    rorbk::Ctrl *h_ctrl;      // pinned mirror
+    double *d_P[2];           // partial A_S x per update chunk [nch][bmax]
+    double *d_axp;            // residual partial products [nseg][m]
+    void *d_r;                // residual (vector type)
+    double *d_bn;             // per-block ||r_t||^2
+    double *d_cn;             // per-chunk ||r||^2
+    uint64_t *d_ckey;         // selection candidates: keys
+    int32_t *d_cidx;          //                        indices
+    uint64_t *d_ckey2;        // second level of candidates
+    int32_t *d_cidx2;
+    int32_t *d_I;             // current greedy set (K)
+    double *d_rI;             // r on the greedy set (K)
+    double *d_y;              // greedy step solution (K)
+    double *d_G;              // Gram partials [nch_g][K*K]
+    double *d_red;            // scratch for norms
+    int32_t *d_tau;           // block draws of the current solve (3 * cap)
+    int64_t tau_cap;
+    // refinement
+    void *d_rhs32;            // float right-hand side of the inner solve
+    void *d_d32;              // float correction
+    double *d_r64;            // FP64 outer residual
+    int64_t refine_inner;
+    double refine_eta;
+    // records
+    int32_t *d_recI;          // greedy sets [cap][K]
+    double *d_recR;           // RRN history [cap]
+    int64_t rec_cap;
+    int64_t rec_iters;        // iterations recorded by the last solve
+    int32_t rec_valid;        // 1 after a RECORD solve, 2 after CHECKPOINT
+    int32_t rec_converged;
+    int64_t ckpt_every;
+    void *d_ckpt;             // x checkpoints (vector type) [(cap/c)+1][n]
+    int64_t ckpt_cap;
+    const void *rec_b;        // b of the recorded solve (CHECKPOINT recompute)
+    uint64_t rec_seed;
+    int32_t rec_vec;          // vector type of the recorded solve
+    double rec_thr;           // stop threshold of the recorded solve
+    // replay
+    int32_t *d_rep_tau;
+    int32_t *d_rep_I;
+    int64_t rep_iters;
+    // events
+    hipEvent_t ev0, ev1;
+};
+
+namespace rorbk {
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  `vec` is VecType; `dt` is the
+// storage dtype of the matrix pointer passed.
+
+hipError_t launch_partition(int64_t m, int64_t k, int64_t *off, int64_t *hoff,
+                            hipStream_t s);
+
+hipError_t launch_sample(uint64_t seed, int64_t j0, int64_t count,
+                         const double *W, int64_t k, int32_t *tau, hipStream_t s);
+
+hipError_t launch_norm2(const void *v, int vec, int64_t len, double *red,
+                        double *out, hipStream_t s);
+
+hipError_t launch_copy_tau(const int32_t *src, int32_t *dst, int64_t count,
+                           hipStream_t s);
+
+// dense setup
+hipError_t launch_setup_proposal_dense(const rorbk_handle_s *h, const void *A,
+                                       int dt, int aligned, double *scratch,
+                                       hipStream_t s);
+hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A,
+                                       int dt, int aligned, int32_t *d_fail,
+                                       hipStream_t s);
+// CSR setup
+hipError_t launch_setup_proposal_csr(rorbk_handle_s *h, const void *vals, int dt,
+                                     double *scratch, int64_t scratch_len,
+                                     hipStream_t s);
+hipError_t launch_block_inverses_csr(const rorbk_handle_s *h, const void *vals,
+                                     int dt, int32_t *d_fail, hipStream_t s);
+hipError_t launch_csr_transpose_blocks(rorbk_handle_s *h, hipStream_t s);
+
+// iteration kernels (dense or CSR chosen from the handle's format)
+struct StepArgs {
+    const void *A;        // matrix values (dtype dt)
+    int dt;
+    int aligned;
+    int vec;
+    const void *b;        // right-hand side (vector type) or NULL (adjoint)
+    void *x;              // iterate (vector type)
+    void *gb;             // adjoint: dL/db accumulator (vector type) or NULL
+    RowSel cur;           // step applied
+    int ymode;            // 0: y from partials + stored inverse; 1: y given; 2: none
+    const double *Pin;    // partials of the current step
+    const double *ygiven;
+    RowSel nxt;           // rows whose partial products are produced
+    double *Pout;
+};
+hipError_t launch_step(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
+
+hipError_t launch_residual(const rorbk_handle_s *h, const void *A, int dt,
+                           int aligned, int vec, const void *x, double *axp,
+                           hipStream_t s);
+
+// selection: builds r = b - sum(axp), block norms, candidates; then the final
+// merge writes I, r_I, the RRN record and the stop flag.
+struct SelectArgs {
+    int vec;
+    const void *b;
+    const double *axp;    // NULL: r = b exactly (top-K of a given vector)
+    int nseg;
+    void *r;
+    int64_t it;           // iteration index for records
+    int record_rrn;
+    double *rec_rrn;
+    int record_I;
+    int32_t *rec_I;       // [it*K]
+    const int32_t *replay_I; // NULL or [it*K]
+    int32_t *I_out;
+    double *rI_out;
+    int stop_test;        // 1: compare with thr2 and set done
+    int skip_topk;        // 1: only norms (refinement outer residual)
+};
+hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream_t s);
+
+hipError_t launch_gram(const rorbk_handle_s *h, const void *A, int dt, int aligned,
+                       const int32_t *idx, int K, double *Gpart, hipStream_t s);
+
+// rhs: rI (forward) or -(sum of partials) (adjoint)
+hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
+                             const double *rI, const double *Pin, double *y,
+                             hipStream_t s);
+
+hipError_t launch_cast_f64_to_f32(const double *src, float *dst, int64_t n,
+                                  hipStream_t s);
+hipError_t launch_axpy_f32_to_f64(const float *d, double *x, int64_t n,
+                                  hipStream_t s);
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t s);
+hipError_t launch_set_refine_ctrl(Ctrl *c, double tol, double eta,
+                                  const double *rout2, double outer_bnorm2,
+                                  hipStream_t s);
+hipError_t launch_init_ctrl(Ctrl *c, double tol, const double *bnorm2, hipStream_t s);
+hipError_t launch_set_thr(Ctrl *c, double thr, hipStream_t s);
+hipError_t launch_axpy_f64(const double *d, double *x, int64_t n, hipStream_t s);
+
+// format-specific pieces behind launch_step / launch_residual / launch_gram
+hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
+hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt,
+                                 int aligned, int vec, const void *x, double *axp,
+                                 hipStream_t s);
+hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt,
+                             const int32_t *idx, int K, double *Gpart, hipStream_t s);
+
+}  // namespace rorbk
