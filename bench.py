@@ -1,0 +1,194 @@
+"""Benchmark: ROR-BK time to relative residual 1e-8 on one MI355X.
+
+Workload: dense tall least-squares A 100000 x 2000 (U diag(s) V^T, s log-spaced
+1..1e-8, cond 1e8), consistent b = A x_star, blocks of 64 rows, lambda 1e-4,
+stop at ||b - A x|| / ||b|| < 1e-8 or after --steps outer iterations (the
+workload's cap is 5000).  A step is one outer ROR-BK iteration: three sampled
+block updates, the full residual pass with per-block norms and the stop test,
+the top-K greedy selection and the greedy block update.
+
+Timed: the mixed-precision solve (FP32 storage for the inner passes, FP64
+outer residual and refinement; `value`) and the all-FP64 solve on the same
+matrix, inputs resident in HBM.  The residual-pass kernel is timed with HIP
+events inside the solve (RORBK_PROFILE).  The FP64 CPU oracle is timed on a
+bounded sample of the same workload on the host cores (cpu_baseline), and the
+GPU solves are compared with it over that sample.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time to rel. residual 1e-8 (s), mixed vs FP64 on GPU; "
+          "residual-pass HBM GB/s")
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="tall_100000x2000")
+    ap.add_argument("--mixed", default="f32", choices=["f32", "bf16"],
+                    help="storage of the inner passes of the mixed solve")
+    ap.add_argument("--inner", type=int, default=50, help="inner iterations per FP64 step")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true",
+                    help="time only the mixed solve (profiling runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
+              "this build has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_02156_amd as P
+    from workloads import make, to_bf16_bits
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    w = make(args.workload)
+    log(f"generated {args.workload} in {time.time() - t0:.1f}s")
+    A64h, bh = w["A"], w["b"]
+    m, n = A64h.shape
+    br, lam, tol, seed = w["block_rows"], w["lam"], w["tol"], w["seed"]
+    A64 = torch.from_numpy(A64h).to(dev)
+    b = torch.from_numpy(bh).to(dev)
+    A32 = A64.float()
+    Abf = torch.from_numpy(to_bf16_bits(A64h).view(np.int16)).view(torch.bfloat16).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.time()
+    s64 = P.Solver(A64, br, lam)
+    torch.cuda.synchronize()
+    t_setup64 = time.time() - t0
+    Amix = A32 if args.mixed == "f32" else Abf
+    t0 = time.time()
+    smix = P.Solver(Amix, br, lam, A64=A64)
+    torch.cuda.synchronize()
+    t_setupmix = time.time() - t0
+    smix.set_refine(args.inner, 1e-4)
+    log(f"setup: fp64 {t_setup64:.3f}s, mixed-{args.mixed} {t_setupmix:.3f}s "
+        f"(k={s64.k}, K={s64.K})")
+
+    K = args.steps
+
+    def run(sol, refine, iters, profile=False):
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = sol.solve(b, x, seed=seed, tol=tol, max_iters=iters, refine=refine,
+                            profile=profile)
+        torch.cuda.synchronize()
+        return x, info, time.perf_counter() - t
+
+    # warmup
+    run(smix, True, args.warmup)
+    if not args.skip_extra:
+        run(s64, False, args.warmup)
+    # timed: mixed (value), then FP64
+    xm, im, tm = run(smix, True, K, profile=True)
+    prof_m = smix.profile()
+    log(f"mixed-{args.mixed}: {tm:.3f}s for {im['iters']} iters, rrn {im['rrn']:.3e}, "
+        f"converged {im['converged']}, refine steps {im['n_refine']}")
+    res = {}
+    if not args.skip_extra:
+        x64, i64, t64 = run(s64, False, K, profile=True)
+        prof_64 = s64.profile()
+        log(f"fp64: {t64:.3f}s for {i64['iters']} iters, rrn {i64['rrn']:.3e}")
+        res["fp64"] = {"time_s": t64, "iters": i64["iters"], "rrn": i64["rrn"],
+                       "converged": i64["converged"],
+                       "resid_kernel_ms": prof_64["inner_ms"],
+                       "resid_GBs": (m * n * 8 + n * 8 + m * 8) / (prof_64["inner_ms"] * 1e-3) / 1e9
+                       if prof_64["inner_ms"] > 0 else None}
+        res["speedup_mixed_vs_fp64"] = t64 / tm
+        xs = w["xstar"]
+        res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
+                                   "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
+
+    # roofline of the dominant kernel: the inner residual pass of the mixed solve
+    es = 4 if args.mixed == "f32" else 2
+    bytes_resid = m * n * es + n * 4 + m * 8       # A once, x, the partial (A x) write
+    ms = prof_m["inner_ms"]
+    achieved = bytes_resid / (ms * 1e-3) / 1e9 if ms > 0 else None
+    roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": None,
+            "kernel": f"k_resid_dense<{args.mixed}>", "bytes_per_launch": bytes_resid,
+            "avg_launch_ms": ms, "launches_timed": prof_m["inner_n"]}
+
+    # CPU baseline: the FP64 oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        probe = O.solve(w, br, lam, bh, seed=seed, tol=tol, max_iters=3, record=False)
+        per = max(probe["t_iter_s"] / 3, 1e-4)
+        N = int(min(2000, max(10, args.cpu_seconds / per)))
+        log(f"oracle: setup {probe['t_setup_s']:.2f}s, {per * 1e3:.1f} ms/iter; sample {N} iters")
+        ref = O.solve(w, br, lam, bh, seed=seed, tol=tol, max_iters=N, record=False)
+        per = ref["t_iter_s"] / max(ref["iters"], 1)
+        cpu = {"value": per * K, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": (f"FP64 oracle setup once ({ref['t_setup_s']:.2f}s, not counted) + "
+                          f"{ref['iters']} outer iterations on the full {m}x{n} matrix; "
+                          f"per-iteration time x {K} steps"),
+               "iters_per_s": 1.0 / per}
+        # GPU solves against the oracle over the same N iterations
+        xg64, _, _ = run(s64, False, N)
+        xgm, _, _ = run(smix, True, N)
+        nr = np.linalg.norm(ref["x"])
+        res["error_vs_oracle"] = {
+            "iters": N,
+            "fp64_rel": float(np.linalg.norm(xg64.cpu().numpy() - ref["x"]) / nr),
+            f"mixed_{args.mixed}_rel": float(np.linalg.norm(xgm.cpu().numpy() - ref["x"]) / nr)}
+        log(f"error vs oracle after {N} iters: {res['error_vs_oracle']}")
+
+    out = {
+        "metric": METRIC,
+        "value": tm,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": tm / max(im["iters"], 1) * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.mixed}+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "block_rows": br,
+                   "lambda": lam, "cond": 1e8, "tol": tol, "cap_iters": K,
+                   "mixed": f"{args.mixed} storage inner passes, FP64 refinement every "
+                            f"{args.inner} inner iterations",
+                   "parallelism": "single GPU"},
+        "reached_tol": bool(im["converged"]),
+        "iters": im["iters"],
+        "rrn_at_end": im["rrn"],
+        "iters_per_s": im["iters"] / tm,
+        "setup_s": {"fp64": t_setup64, "mixed": t_setupmix},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(res)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

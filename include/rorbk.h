@@ -93,6 +93,9 @@ typedef struct rorbk_handle_s *rorbk_handle;
 #define RORBK_REPLAY 4u      /* take tau and the greedy sets from set_replay  */
 #define RORBK_CHECKPOINT 8u  /* keep x every checkpoint_every iterations and
                                 recompute the greedy sets during backward     */
+#define RORBK_PROFILE 16u    /* time the residual-pass kernel with HIP events
+                                (one launch in every 16 iterations, plus every
+                                FP64 outer pass); read with ror_bk_get_profile */
 
 /* Setup (Algorithm 1, first four steps; Section 3.1 for the stored block
  * inverses).  Partitions A into k = floor(m / block_rows) contiguous blocks of
@@ -188,6 +191,12 @@ int ror_bk_set_replay(rorbk_handle h, const int32_t *tau_host,
  * (default 50) and the inner relative stop eta (default 1e-4; the inner solve
  * also stops once its residual is below tol * ||b||). */
 int ror_bk_set_refine(rorbk_handle h, int64_t inner_iters, double eta);
+
+/* Residual-pass timings of the last RORBK_PROFILE solve: out[0] = mean
+ * duration (ms) of the sampled inner (working-precision) residual launches,
+ * out[1] = their count, out[2] = mean duration (ms) of the FP64 outer residual
+ * launches of a REFINE solve, out[3] = their count. */
+int ror_bk_get_profile(rorbk_handle h, double *out4_host);
 
 /* Static description of a status code. */
 const char *ror_bk_error_string(int code);

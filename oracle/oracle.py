@@ -69,7 +69,7 @@ def lib():
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [P, C.c_int64, C.c_double, P, P, C.c_uint64,
                                 C.c_double, C.c_int64, C.c_int64, P, P, P,
-                                P, P, P, P, P]
+                                P, P, P, P, P, P]
         L.orc_backward.restype = C.c_int
         L.orc_backward.argtypes = [P, C.c_int64, C.c_double, P, P, C.c_int64,
                                    C.c_int32, P, P]
@@ -263,14 +263,15 @@ def solve(A, block_rows: int, mu: float, b, x0=None, seed: int = 0,
     rr = np.zeros(max_iters) if record else None
     ints = np.zeros(2, dtype=np.int64)
     rrn = np.zeros(1)
+    times = np.zeros(2)
     rc = lib().orc_solve(M.ptr, block_rows, mu, _p(b), _p(x), seed & ((1 << 64) - 1),
                          tol, max_iters, start_iter, _p(Wa), _p(rt), _p(rI),
-                         _p(tau), _p(Is), _p(rr), _p(ints), _p(rrn))
+                         _p(tau), _p(Is), _p(rr), _p(ints), _p(rrn), _p(times))
     if rc:
         raise OracleError(rc, "solve")
     it = int(ints[0])
     out = {"x": x, "iters": it, "converged": bool(ints[1]), "rrn": float(rrn[0]),
-           "K": K, "k": k}
+           "K": K, "k": k, "t_setup_s": float(times[0]), "t_iter_s": float(times[1])}
     if record:
         out["tau"] = tau[: 3 * it].copy()
         out["I"] = Is[: it * K].reshape(it, K).copy()

@@ -23,8 +23,10 @@
  *  - a zero centroid has C(t,t) = 1 and C(t,j) = 0 for j != t.
  * Parity pins for every function live in the test suite.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
+#include <time.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -441,15 +443,25 @@ int orc_topk(const double *r, int64_t m, int64_t K, int32_t *idx)
  * replay_tau / replay_I (NULL = free running) inject the selections;
  * rec_tau, rec_I, rec_rrn (NULL = off) receive them, indexed from start_iter.
  * W_in, if not NULL, replaces the proposal table (k entries).
- * out_ints = {iterations run, converged}; out_rrn = last measured RRN. */
+ * out_ints = {iterations run, converged}; out_rrn = last measured RRN;
+ * out_times (NULL = off) = {setup seconds, iteration seconds} (wall clock). */
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
 int orc_solve(const orc_matrix *A, int64_t block_rows, double mu,
               const double *b, double *x, uint64_t seed, double tol,
               int64_t max_iters, int64_t start_iter,
               const double *W_in,
               const int32_t *replay_tau, const int32_t *replay_I,
               int32_t *rec_tau, int32_t *rec_I, double *rec_rrn,
-              int64_t *out_ints, double *out_rrn)
+              int64_t *out_ints, double *out_rrn, double *out_times)
 {
+    const double t_start = now_s();
+    double t_iter = 0.0;
     const int64_t m = A->m, n = A->n;
     int64_t k = orc_num_blocks(m, block_rows);
     if (k <= 0 || mu < 0.0) return ORC_ERR_ARG;
@@ -496,6 +508,7 @@ int orc_solve(const orc_matrix *A, int64_t block_rows, double mu,
     double bnorm2 = 0.0;
     for (int64_t i = 0; i < m; ++i) bnorm2 += b[i] * b[i];
     const double thresh = tol * sqrt(bnorm2);
+    t_iter = now_s();
     int64_t it = 0;
     int converged = 0;
     double rrn = NAN;
@@ -535,6 +548,11 @@ int orc_solve(const orc_matrix *A, int64_t block_rows, double mu,
     }
     if (out_ints) { out_ints[0] = it; out_ints[1] = converged; }
     if (out_rrn) *out_rrn = rrn;
+    if (out_times) {
+        const double t_end = now_s();
+        out_times[0] = t_iter - t_start;
+        out_times[1] = t_end - t_iter;
+    }
 done:
     if (Lt) for (int64_t t = 0; t < k; ++t) free(Lt[t]);
     free(off); free(S); free(pbar); free(W); free(Lt); free(r); free(ws);

@@ -10,9 +10,10 @@ from __future__ import annotations
 import torch
 
 from .binding import *  # noqa: F401,F403
-from .binding import (RORBK_CHECKPOINT, RORBK_RECORD, RORBK_REFINE, RORBK_REPLAY,
+from .binding import (RORBK_CHECKPOINT, RORBK_PROFILE, RORBK_RECORD, RORBK_REFINE, RORBK_REPLAY,
                       RorBkError, lib, ror_bk_backward, ror_bk_destroy,
-                      ror_bk_get_block_inverse, ror_bk_get_record, ror_bk_get_setup,
+                      ror_bk_get_block_inverse, ror_bk_get_profile, ror_bk_get_record,
+                      ror_bk_get_setup,
                       ror_bk_get_sizes, ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
                       ror_bk_set_refine, ror_bk_set_replay, ror_bk_setup, ror_bk_solve,
                       ror_bk_topk)
@@ -43,7 +44,7 @@ class Solver:
 
     def solve(self, b, x=None, *, seed: int = 0, tol: float = 1e-8, max_iters: int = 1000,
               start_iter: int = 0, refine: bool = False, record: bool = False,
-              replay: bool = False, checkpoint_every: int = 0):
+              replay: bool = False, checkpoint_every: int = 0, profile: bool = False):
         """Run ROR-BK from x (zeros if None; updated in place).  Returns (x, info)."""
         vt = self.vec_dtype(refine)
         if x is None:
@@ -51,7 +52,8 @@ class Solver:
         if b.dtype != vt or x.dtype != vt:
             raise TypeError(f"b and x must be {vt} for this solve")
         flags = (RORBK_REFINE if refine else 0) | (RORBK_RECORD if record else 0) | \
-                (RORBK_REPLAY if replay else 0) | (RORBK_CHECKPOINT if checkpoint_every else 0)
+                (RORBK_REPLAY if replay else 0) | (RORBK_CHECKPOINT if checkpoint_every else 0) | \
+                (RORBK_PROFILE if profile else 0)
         self._b_keep = b
         info = ror_bk_solve(self.h, b, x, seed, tol, max_iters, start_iter, flags,
                             checkpoint_every)
@@ -87,6 +89,9 @@ class Solver:
         bn = torch.empty(self.k, dtype=torch.float64, device=b.device)
         rrn = ror_bk_residual(self.h, b, x, r, bn, use_f64_master)
         return r, bn, rrn
+
+    def profile(self) -> dict:
+        return ror_bk_get_profile(self.h)
 
     def record(self) -> dict:
         return ror_bk_get_record(self.h, self.K)

@@ -28,13 +28,14 @@ RORBK_MAX_BLOCK_ROWS = 160
 RORBK_DENSE, RORBK_CSR = 0, 1
 RORBK_F64, RORBK_F32, RORBK_BF16 = 0, 1, 2
 RORBK_REFINE, RORBK_RECORD, RORBK_REPLAY, RORBK_CHECKPOINT = 1, 2, 4, 8
+RORBK_PROFILE = 16
 
 EXPORTS = [
     "ror_bk_setup", "ror_bk_solve", "ror_bk_backward", "ror_bk_destroy",
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
     "ror_bk_get_block_inverse", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
     "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
-    "ror_bk_error_string", "ror_bk_last_error_message",
+    "ror_bk_get_profile", "ror_bk_error_string", "ror_bk_last_error_message",
 ]
 
 
@@ -93,6 +94,7 @@ def lib():
             "ror_bk_get_record": (C.c_int, [P, P, P, P, P]),
             "ror_bk_set_replay": (C.c_int, [P, P, P, I64]),
             "ror_bk_set_refine": (C.c_int, [P, I64, D]),
+            "ror_bk_get_profile": (C.c_int, [P, P]),
             "ror_bk_error_string": (C.c_char_p, [C.c_int]),
             "ror_bk_last_error_message": (C.c_char_p, []),
         }
@@ -262,6 +264,13 @@ def ror_bk_set_replay(h, tau, I, iters: int):
 
 def ror_bk_set_refine(h, inner_iters: int, eta: float):
     _check(lib().ror_bk_set_refine(h, int(inner_iters), float(eta)), "ror_bk_set_refine")
+
+
+def ror_bk_get_profile(h) -> dict:
+    out = np.zeros(4)
+    _check(lib().ror_bk_get_profile(h, _np_ptr(out)), "ror_bk_get_profile")
+    return {"inner_ms": out[0], "inner_n": int(out[1]), "outer_ms": out[2],
+            "outer_n": int(out[3])}
 
 
 def ror_bk_error_string(code: int) -> str:

@@ -116,7 +116,7 @@ __device__ __forceinline__ uint64_t key_of(float v) {
     return (uint64_t)(__float_as_uint(v) & 0x7fffffffu);
 }
 
-constexpr int SEL_T = 256;          // threads of the selection kernels
+constexpr int SEL_T = 512;          // threads of the selection kernels
 constexpr int SEL_CHUNK = 4096;     // rows per selection chunk (upper bound)
 constexpr int SEL_MERGE = 8192;     // candidates per merge workgroup
 constexpr int SEL_BPC = 256;        // blocks per selection chunk (upper bound)
@@ -143,14 +143,17 @@ __device__ __forceinline__ uint64_t block_exscan_u64(uint64_t v, uint64_t *sh, u
     return base + inc - v;
 }
 
-// Radix select over keys[0..N) in LDS: finds the K-th largest key T and the
-// number `need` of elements equal to T that complete the top K.
-__device__ void radix_select(const uint64_t *keys, int N, int K, int nbits,
-                             uint64_t *T_out, int *need_out) {
+// Radix select over keys[0..N) in LDS, most significant byte first: finds a
+// masked threshold (T, mask) and the number `need` of elements whose masked key
+// equals T that complete the top K (elements with a larger masked key are all
+// in).  Stops as soon as the boundary digit's bucket holds exactly `need`
+// elements; otherwise continues to the last byte (then T is the exact K-th key).
+__device__ void radix_select(const uint64_t *keys, int N, int K, int nbits, uint64_t *T_out,
+                             uint64_t *mask_out, int *need_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int s_need;
-    if (threadIdx.x == 0) { s_prefix = 0; s_mask = 0; s_need = K; }
+    __shared__ int s_need, s_stop;
+    if (threadIdx.x == 0) { s_prefix = 0; s_mask = 0; s_need = K; s_stop = 0; }
     __syncthreads();
     for (int shift = nbits - 8; shift >= 0; shift -= 8) {
         for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
@@ -179,44 +182,51 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int nbits,
             if (lane == top) {
                 uint32_t above = suf - ls;
                 int bin = 4 * lane;
+                uint32_t inbin = h[0];
                 for (int u = 3; u >= 0; --u) {
-                    if (above + h[u] >= (uint32_t)need) { bin = 4 * lane + u; break; }
+                    if (above + h[u] >= (uint32_t)need) { bin = 4 * lane + u; inbin = h[u]; break; }
                     above += h[u];
                 }
                 s_need = need - (int)above;
                 s_prefix = prefix | ((uint64_t)bin << shift);
                 s_mask = mask | ((uint64_t)255 << shift);
+                s_stop = (inbin == (uint32_t)(need - (int)above)) ? 1 : 0;
             }
         }
         __syncthreads();
+        if (s_stop) break;
     }
     *T_out = s_prefix;
+    *mask_out = s_mask;
     *need_out = s_need;
     __syncthreads();
 }
 
-// Emit, in ascending index order, every element with key > T and the first
-// `need` elements with key == T.  keys/ids in LDS (ids == NULL: position).
+// Emit, in ascending index order, every element whose masked key exceeds T
+// and the first `need` elements whose masked key equals T (K in total).
+// keys/ids in LDS (ids == NULL: the position); outputs get base added.
 __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, int K, uint64_t T,
-                             int need, uint64_t *okey, int32_t *oidx, int32_t base) {
+                             uint64_t mask, int need, uint64_t *okey, int32_t *oidx,
+                             int32_t base) {
     __shared__ uint64_t sh[16];
     const int per = (N + blockDim.x - 1) / blockDim.x;
     const int a = threadIdx.x * per, e = (a + per < N) ? a + per : N;
     uint32_t gt = 0, eq = 0;
     for (int i = a; i < e; ++i) {
-        gt += keys[i] > T;
-        eq += keys[i] == T;
+        const uint64_t mk = keys[i] & mask;
+        gt += mk > T;
+        eq += mk == T;
     }
     uint64_t tot;
     const uint64_t ex = block_exscan_u64(((uint64_t)gt << 32) | eq, sh, &tot);
     uint32_t g = (uint32_t)(ex >> 32), q = (uint32_t)(ex & 0xffffffffu);
     for (int i = a; i < e; ++i) {
-        const uint64_t kk = keys[i];
+        const uint64_t kk = keys[i], mk = kk & mask;
         int pos = -1;
-        if (kk > T) {
+        if (mk > T) {
             pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
             ++g;
-        } else if (kk == T) {
+        } else if (mk == T) {
             if (q < (uint32_t)need) pos = (int)(g + q);
             ++q;
         }
@@ -232,41 +242,58 @@ __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, in
 // and the chunk's local top-K candidates (keys, global row indices).
 template <typename V>
 __global__ __launch_bounds__(SEL_T) void k_select_chunk(
-    const V *__restrict__ b, const double *__restrict__ axp, int nseg, int64_t m,
-    const int64_t *__restrict__ off, int64_t k, int64_t bpc, int K, V *__restrict__ r,
-    double *__restrict__ bn, double *__restrict__ cn, uint64_t *__restrict__ ckey,
-    int32_t *__restrict__ cidx, int do_topk, const Ctrl *__restrict__ ctrl) {
+    const V *__restrict__ b, const double *__restrict__ axp, int nseg, int64_t m, int64_t q,
+    int64_t rem, int64_t k, int64_t bpc, int K, V *__restrict__ r, double *__restrict__ bn,
+    double *__restrict__ cn, uint64_t *__restrict__ ckey, int32_t *__restrict__ cidx,
+    int do_topk, const Ctrl *__restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
     __shared__ uint64_t keys[SEL_CHUNK];
     __shared__ double vals[SEL_CHUNK];
     __shared__ double s_bn[SEL_BPC];
     const int64_t t0 = (int64_t)blockIdx.x * bpc;
     const int64_t t1 = (t0 + bpc < k) ? t0 + bpc : k;
-    const int64_t r0 = off[t0], r1 = off[t1];
+    const int64_t r0 = blk_start(t0, q, rem), r1 = blk_start(t1, q, rem);
     const int N = (int)(r1 - r0);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        const int64_t row = r0 + i;
-        V s = (V)0;
-        if (axp) {
-            double a = 0.0;
-            for (int sg = 0; sg < nseg; ++sg) a += axp[(int64_t)sg * m + row];
-            s = (V)((double)b[row] - a);
-        } else {
-            s = b[row];
+    constexpr int PER = SEL_CHUNK / SEL_T;
+    // every load of the chunk in flight at once
+    V bv[PER];
+    double av[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * SEL_T;
+        bv[u] = (i < N) ? b[r0 + i] : (V)0;
+        av[u] = 0.0;
+    }
+    if (axp) {
+        for (int sg = 0; sg < nseg; ++sg) {
+            double t[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = threadIdx.x + u * SEL_T;
+                t[u] = (i < N) ? axp[(int64_t)sg * m + r0 + i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) av[u] += t[u];
         }
-        r[row] = s;
-        vals[i] = (double)s;
-        keys[i] = key_of(s);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * SEL_T;
+        if (i < N) {
+            const V s = axp ? (V)((double)bv[u] - av[u]) : bv[u];
+            r[r0 + i] = s;
+            vals[i] = (double)s;
+            keys[i] = key_of(s);
+        }
     }
     __syncthreads();
     // per-block squared norms: one wave per block, lanes stride the rows
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int64_t t = t0 + w; t < t1; t += nw) {
+        const int64_t s0 = blk_start(t, q, rem) - r0;
+        const int bt = blk_rows(t, q, rem);
         double s = 0.0;
-        for (int64_t i = off[t] + lane; i < off[t + 1]; i += 64) {
-            const double v = vals[i - r0];
-            s = __builtin_fma(v, v, s);
-        }
+        for (int i = lane; i < bt; i += 64) s = __builtin_fma(vals[s0 + i], vals[s0 + i], s);
         s = group_sum(s, 64);
         if (lane == 0) { bn[t] = s; s_bn[t - t0] = s; }
     }
@@ -277,10 +304,10 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
         cn[blockIdx.x] = s;
     }
     if (!do_topk) return;
-    uint64_t T;
+    uint64_t T, mask;
     int need;
-    radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &need);
-    compact_topk(keys, nullptr, N, K, T, need, ckey + (int64_t)blockIdx.x * K,
+    radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &mask, &need);
+    compact_topk(keys, nullptr, N, K, T, mask, need, ckey + (int64_t)blockIdx.x * K,
                  cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
 }
 
@@ -298,34 +325,49 @@ __global__ __launch_bounds__(SEL_T) void k_select_merge(
     if (ctrl->done) return;
     __shared__ uint64_t keys[SEL_MERGE];
     __shared__ int32_t ids[SEL_MERGE];
+    __shared__ double s_cn[SEL_MERGE / 4];
     __shared__ int s_stop;
     const int l0 = blockIdx.x * lists_per_group;
     const int l1 = (l0 + lists_per_group < nlists) ? l0 + lists_per_group : nlists;
     const int N = (l1 - l0) * K;
+    constexpr int NCN = SEL_MERGE / 4;
+    if (final_level) {
+        for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
+    }
     if (do_topk) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            keys[i] = ckey[(int64_t)l0 * K + i];
-            ids[i] = cidx[(int64_t)l0 * K + i];
+        constexpr int PER = SEL_MERGE / SEL_T;
+        uint64_t kv[PER];
+        int32_t iv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * SEL_T;
+            kv[u] = (i < N) ? ckey[(int64_t)l0 * K + i] : 0;
+            iv[u] = (i < N) ? cidx[(int64_t)l0 * K + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * SEL_T;
+            if (i < N) { keys[i] = kv[u]; ids[i] = iv[u]; }
         }
         __syncthreads();
-        uint64_t T;
+        uint64_t T, mask;
         int need;
-        radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &need);
+        radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &mask, &need);
         if (!final_level) {
-            compact_topk(keys, ids, N, K, T, need, okey + (int64_t)blockIdx.x * K,
+            compact_topk(keys, ids, N, K, T, mask, need, okey + (int64_t)blockIdx.x * K,
                          oidx + (int64_t)blockIdx.x * K, 0);
             return;
         }
         __shared__ uint64_t fk[MAXB];
         __shared__ int32_t fi[MAXB];
-        compact_topk(keys, ids, N, K, T, need, fk, fi, 0);
+        compact_topk(keys, ids, N, K, T, mask, need, fk, fi, 0);
         __syncthreads();
         for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double rn2 = 0.0;
-        for (int c = 0; c < ncn; ++c) rn2 += cn[c];
+        for (int c = 0; c < ncn; ++c) rn2 += (c < NCN) ? s_cn[c] : cn[c];
         const double rn = sqrt(rn2);
         ctrl->rnorm2 = rn2;
         ctrl->last_it = it;
@@ -361,12 +403,12 @@ hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream
     const int do_topk = (!a.skip_topk && !a.replay_I) ? 1 : 0;
     if (a.vec == VEC_F64)
         hipLaunchKernelGGL(k_select_chunk<double>, dim3(L.nch_s), dim3(SEL_T), 0, s,
-                           (const double *)a.b, a.axp, a.nseg, L.m, h->d_off, L.k, L.bpc, K,
+                           (const double *)a.b, a.axp, a.nseg, L.m, L.q, L.rem, L.k, L.bpc, K,
                            (double *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
                            h->d_ctrl);
     else
         hipLaunchKernelGGL(k_select_chunk<float>, dim3(L.nch_s), dim3(SEL_T), 0, s,
-                           (const float *)a.b, a.axp, a.nseg, L.m, h->d_off, L.k, L.bpc, K,
+                           (const float *)a.b, a.axp, a.nseg, L.m, L.q, L.rem, L.k, L.bpc, K,
                            (float *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
                            h->d_ctrl);
     hipError_t e = hipGetLastError();
@@ -412,58 +454,91 @@ hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream
 }
 
 // ------------------------------------------------------ greedy block solve --
-// (A_I A_I^T + lambda I) y = rhs, the greedy step of Algorithm 1: the Gram
-// partials of the column chunks are summed in chunk order, lambda is added to
-// the diagonal, the packed FP64 Cholesky factor is formed in LDS and the two
-// triangular solves run on one wave.  rhs = r_I (forward) or, for the adjoint,
-// -(sum of the partial products A_I g).
-__global__ __launch_bounds__(256) void k_chol_solve(const double *__restrict__ Gpart, int nch,
-                                                    int K, double lambda,
-                                                    const double *__restrict__ rI,
-                                                    const double *__restrict__ Pin, int nchP,
-                                                    int bmax, double *__restrict__ y,
-                                                    Ctrl *__restrict__ ctrl) {
+// (A_I A_I^T + lambda I) y = rhs, the greedy step of Algorithm 1: the packed
+// Gram partials of the column chunks are summed in chunk order (loads in
+// flight together), lambda is added to the diagonal, and the LDL^T solve runs
+// on one wave (K <= 64, MT = 0) or on MT x MT register tiles (larger K).  rhs = r_I (forward) or, for the
+// adjoint, -(sum of the partial products A_I g).
+template <int MT, int NTH>
+__global__ __launch_bounds__(NTH) void k_chol_solve(const double *__restrict__ Gpart, int nch,
+                                                     int K, double lambda,
+                                                     const double *__restrict__ rI,
+                                                     const double *__restrict__ Pin, int nchP,
+                                                     int bmax, double *__restrict__ y,
+                                                     Ctrl *__restrict__ ctrl) {
     if (ctrl->done) return;
-    __shared__ double Lp[PACKED_MAX];
-    __shared__ double rhs[MAXB];
-    const int tot = K * (K + 1) / 2;
-    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-        int i = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
-        while (i * (i + 1) / 2 > f) --i;
-        while ((i + 1) * (i + 2) / 2 <= f) ++i;
-        const int j = f - i * (i + 1) / 2;
-        double g = 0.0;
-        for (int c = 0; c < nch; ++c) g += Gpart[(int64_t)c * K * K + i * K + j];
-        if (i == j) g += lambda;
-        Lp[f] = g;
+    __shared__ double Gp[PACKED_MAX];
+    __shared__ double z[MAXB];
+    __shared__ double colbuf[2 * MAXB];
+    const int KP = K * (K + 1) / 2;
+    for (int f0 = 0; f0 < KP; f0 += NTH * 4) {
+        double g[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c0 = 0; c0 < nch; c0 += 8) {
+            double t[4][8];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int f = f0 + threadIdx.x + u * NTH;
+                    t[u][c] = (f < KP && c0 + c < nch) ? Gpart[(int64_t)(c0 + c) * KP + f] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < 8; ++c) g[u] += t[u][c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = f0 + threadIdx.x + u * NTH;
+            if (f < KP) Gp[f] = g[u];
+        }
     }
     for (int p = threadIdx.x; p < K; p += blockDim.x) {
         if (rI) {
-            rhs[p] = rI[p];
+            z[p] = rI[p];
         } else {
             double s = 0.0;
             for (int c = 0; c < nchP; ++c) s += Pin[(int64_t)c * bmax + p];
-            rhs[p] = -s;
+            z[p] = -s;
         }
     }
     __syncthreads();
-    if (!chol_packed(Lp, K)) {
+    for (int p = threadIdx.x; p < K; p += blockDim.x) Gp[pk(p, p)] += lambda;
+    __syncthreads();
+    if (MT == 0) {
+        // K <= 64: one wave from here on; the other waves leave and no block
+        // barrier follows
+        if (threadIdx.x >= 64) return;
+        __shared__ double Lc[64 * 65];
+        if (!ldl_wave64(Gp, z, K, colbuf, Lc)) {
+            if (threadIdx.x == 0) {
+                ctrl->status = RORBK_ERR_NOT_SPD;
+                ctrl->done = 1;
+            }
+            return;
+        }
+        for (int p = threadIdx.x; p < K; p += 64) y[p] = z[p];
+        return;
+    }
+    if (!ldl_solve<(MT > 0 ? MT : 4)>(Gp, z, K, colbuf)) {
         if (threadIdx.x == 0) {
             ctrl->status = RORBK_ERR_NOT_SPD;
             ctrl->done = 1;
         }
         return;
     }
-    chol_solve_wave(Lp, K, rhs, rhs);
-    __syncthreads();
-    for (int p = threadIdx.x; p < K; p += blockDim.x) y[p] = rhs[p];
+    for (int p = threadIdx.x; p < K; p += blockDim.x) y[p] = z[p];
 }
 
 hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                              const double *rI, const double *Pin, double *y, hipStream_t s) {
     const Layout &L = h->L;
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K, h->lambda, rI,
-                       Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
+    if (K <= 64)
+        hipLaunchKernelGGL((k_chol_solve<0, 256>), dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K,
+                           h->lambda, rI, Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
+    else
+        hipLaunchKernelGGL((k_chol_solve<8, 512>), dim3(1), dim3(512), 0, s, Gpart, L.nch_g, K,
+                           h->lambda, rI, Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
     return hipGetLastError();
 }
 

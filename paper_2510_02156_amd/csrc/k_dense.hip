@@ -9,16 +9,17 @@ constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 
 // ------------------------------------------------------------ residual pass --
 // Algorithm 1, r = b - A x: the products (A x)_i over one 2048-column segment.
-// One wave per row, each lane holding its 32 entries of x in registers and
-// streaming the row with 16-byte non-temporal loads; the lane sums are combined
-// by a fixed butterfly.  axp[seg][i] = partial (A x)_i; the selection kernel
-// subtracts the segment sum from b.  Grid: x = row groups (4 waves of `rpw`
-// rows), y = segments.
-template <typename T, typename V, bool AL>
+// A persistent grid (a few workgroups per CU) walks the rows: wave w takes rows
+// w*ROWS, w*ROWS + nwaves*ROWS, ..., ROWS rows in flight at a time.  Each lane
+// keeps its 32 entries of x in registers and streams the row with 16-byte
+// non-temporal loads; lane sums are combined by a fixed butterfly.
+// axp[seg][i] = partial (A x)_i; the selection kernel subtracts the segment sum
+// from b.  Grid: x = workgroups, y = segments.
+template <typename T, typename V, bool AL, int ROWS>
 __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
                                                      const V *__restrict__ x,
-                                                     double *__restrict__ axp, int rpw,
+                                                     double *__restrict__ axp,
                                                      const Ctrl *__restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
     constexpr int VW = Tr<T>::VW;
@@ -33,42 +34,49 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 #pragma unroll
         for (int e = 0; e < VW; ++e) xr[s][e] = (col + e < n) ? x[col + e] : (V)0;
     }
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * rpw;
-    for (int rr = 0; rr < rpw; ++rr) {
-        const int64_t i = r0 + rr;
-        if (i >= m) break;
-        const T *row = A + i * ld;
-        V acc = (V)0;
+    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t stride = nwaves * ROWS;
+    for (int64_t i = ((int64_t)blockIdx.x * 4 + w) * ROWS; i < m; i += stride) {
+        V acc[ROWS];
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr) acc[rr] = (V)0;
 #pragma unroll
         for (int s = 0; s < NVL; ++s) {
             const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
-            if (col < n) {
-                V a[VW];
-                load_vec_nt<T, V, AL>(row, col, n, a);
 #pragma unroll
-                for (int e = 0; e < VW; ++e) acc = fmaT(a[e], xr[s][e], acc);
+            for (int rr = 0; rr < ROWS; ++rr) {
+                if (i + rr < m && col < n) {
+                    V a[VW];
+                    load_vec_nt<T, V, AL>(A + (i + rr) * ld, col, n, a);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) acc[rr] = fmaT(a[e], xr[s][e], acc[rr]);
+                }
             }
         }
-        acc = group_sum(acc, WAVE);
-        if (lane == 0) axp[seg * m + i] = (double)acc;
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr) {
+            const V sres = group_sum(acc[rr], WAVE);
+            if (lane == 0 && i + rr < m) axp[seg * m + i + rr] = (double)sres;
+        }
     }
 }
 
 // ------------------------------------------------------------ block step --
 // One regularised block update (Lemma 2's update rule, Algorithm 1) fused with
-// the partial products of the next step.  Workgroup w owns columns
-// [w*wu, (w+1)*wu):
+// the partial products of the next step.  Workgroup w owns the columns
+// [w*wu, (w+1)*wu), split into 128-column slabs; a slab is read by NV lanes
+// (16 bytes each) per row, and 16 row groups share the rows of a step:
 //   1. (ymode 0) r_S = b_S - sum_ch Pin[ch][.] (chunk order), y = H_t r_S with
 //      the stored inverse H_t of block t; (ymode 1) y given;
-//   2. x[cols] += A_S[:, cols]^T y (rows split over row groups, summed in
-//      group order);
+//   2. x[cols] += A_S[:, cols]^T y (row groups summed in group order);
 //   3. Pout[w][p] = A_{S'}[p, cols] . x[cols] for the next step's rows S'.
-// With b == NULL the step is the adjoint one (see the backward pass): then
-// workgroup 0 also accumulates gb[S] -= y.
+// Every independent load (both row sets' first slab, the partials, the stored
+// inverse) is issued before the first barrier, so a step costs a few memory
+// round trips.  With b == NULL the step is the adjoint one (see the backward
+// pass): then workgroup 0 also accumulates gb[S] -= y.
 struct StepP {
     const void *A;
-    int64_t ld, m, n;
-    const int64_t *off;
+    int64_t ld, m, n, q, rem;
     const int32_t *tau;
     RowSel cur;
     int ymode;
@@ -76,7 +84,6 @@ struct StepP {
     int nch;
     int bmax;
     const double *H;
-    const int64_t *hoff;
     const void *b;
     void *x;
     void *gb;
@@ -87,88 +94,165 @@ struct StepP {
     const Ctrl *ctrl;
 };
 
-template <typename V>
-__device__ __forceinline__ void resolve_rows(const RowSel &s, const int64_t *off, const int32_t *tau,
-                                             int64_t *start, int *cnt, int *t) {
-    if (s.kind == 0) {
-        *t = tau[s.tau_index];
-        *start = off[*t];
-        *cnt = (int)(off[*t + 1] - *start);
-    } else if (s.kind == 1) {
-        *t = -1;
-        *start = 0;
-        *cnt = s.count;
-    } else {
-        *t = -1;
-        *start = 0;
-        *cnt = 0;
-    }
-}
+constexpr int STEP_T = 512;  // threads of the block step
 
-template <typename T, typename V, bool AL>
-__global__ __launch_bounds__(256) void k_step_dense(StepP p) {
-    if (p.ctrl->done) return;
+// row groups of the block step for storage T (8 for FP64, 16 FP32, 32 BF16)
+template <typename T>
+constexpr int step_groups() { return STEP_T / (128 / Tr<T>::VW); }
+
+template <typename T, typename V, bool AL, int RPT>
+__global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
     constexpr int VW = Tr<T>::VW;
-    constexpr int NV = 128 / VW;   // threads across a 128-column slab
-    constexpr int G = 256 / NV;    // row groups
+    constexpr int NV = 128 / VW;       // lanes across a slab
+    constexpr int G = step_groups<T>();
+    constexpr int NT = STEP_T;
+    constexpr int TPR = NT / 128;      // threads per row in the y phase
     const T *__restrict__ A = (const T *)p.A;
     V *__restrict__ x = (V *)p.x;
     const V *__restrict__ b = (const V *)p.b;
     const int tid = threadIdx.x, g = tid / NV, v = tid % NV;
+
+    int tc = -1, cnt = 0, ncnt = 0;
+    int64_t cst = 0, nst = 0;
+    if (p.cur.kind == 0) {
+        tc = p.tau[p.cur.tau_index];
+        cst = blk_start(tc, p.q, p.rem);
+        cnt = blk_rows(tc, p.q, p.rem);
+    } else if (p.cur.kind == 1) {
+        cnt = p.cur.count;
+    }
+    if (p.nxt.kind == 0) {
+        const int tn = p.tau[p.nxt.tau_index];
+        nst = blk_start(tn, p.q, p.rem);
+        ncnt = blk_rows(tn, p.q, p.rem);
+    } else if (p.nxt.kind == 1) {
+        ncnt = p.nxt.count;
+    }
+    if (p.ctrl->done) return;
+    const bool upd = p.ymode != 2;
     const int64_t c0 = (int64_t)blockIdx.x * p.wu;
     const int64_t c1 = (c0 + p.wu < p.n) ? c0 + p.wu : p.n;
     const int wcols = (int)(c1 - c0);
+
     __shared__ V s_x[1024];
     __shared__ V s_red[G][128];
     __shared__ double s_r[MAXB], s_y[MAXB];
-    __shared__ int64_t s_row[MAXB];
 
-    int64_t start;
-    int cnt, t;
-    resolve_rows<V>(p.cur, p.off, p.tau, &start, &cnt, &t);
-    for (int i = tid; i < cnt; i += 256)
-        s_row[i] = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : start + i;
-    for (int c = tid; c < wcols; c += 256) s_x[c] = x[c0 + c];
-    __syncthreads();
+    int32_t crow[RPT], nrow[RPT];   // row ids (m < 2^31), -1 = none
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int qq = g + G * r;
+        crow[r] = (upd && qq < cnt) ? (p.cur.kind == 1 ? p.cur.idx[qq] : (int32_t)(cst + qq)) : -1;
+        nrow[r] = (qq < ncnt) ? (p.nxt.kind == 1 ? p.nxt.idx[qq] : (int32_t)(nst + qq)) : -1;
+    }
+    uvec4 ua[RPT], un[RPT];
+    const uvec4 zero4 = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int64_t col = c0 + (int64_t)v * VW;
+        ua[r] = (crow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, col, c1) : zero4;
+        un[r] = (nrow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, col, c1) : zero4;
+    }
+    for (int c = tid; c < wcols; c += NT) s_x[c] = x[c0 + c];
 
     if (p.ymode == 0) {
-        for (int i = tid; i < cnt; i += 256) {
+        const double *__restrict__ H = p.H + blk_hoff(tc, p.q, p.rem);
+        // prefetch the first HP stored-inverse terms of row tid / TPR
+        constexpr int HP = (64 / TPR < 16) ? 64 / TPR : 16;
+        double hpre[HP];
+        {
+            const int i = tid / TPR, qd = tid % TPR;
+#pragma unroll
+            for (int u = 0; u < HP; ++u) {
+                const int j = qd + TPR * u;
+                hpre[u] = (i < cnt && j < cnt) ? H[(int64_t)j * cnt + i] : 0.0;
+            }
+        }
+        for (int base = 0; base < cnt; base += 128) {
+            const int i = base + tid / TPR, qd = tid % TPR;
+            double s = 0.0, bi = 0.0;
+            if (i < cnt) {
+                const int64_t row = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : cst + i;
+                bi = b ? (double)b[row] : 0.0;
+                for (int cb = 0; cb < p.nch; cb += 8 * TPR) {
+                    double t[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int ch = cb + qd + TPR * u;
+                        t[u] = (ch < p.nch) ? p.Pin[(int64_t)ch * p.bmax + i] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s += t[u];
+                }
+            }
+            s = group_sum(s, TPR);
+            if (i < cnt && qd == 0) s_r[i] = bi - s;
+        }
+        __syncthreads();
+        for (int base = 0; base < cnt; base += 128) {
+            const int i = base + tid / TPR, qd = tid % TPR;
             double s = 0.0;
-            for (int ch = 0; ch < p.nch; ++ch) s += p.Pin[(int64_t)ch * p.bmax + i];
-            const double bi = b ? (double)b[s_row[i]] : 0.0;
-            s_r[i] = bi - s;
+            if (i < cnt) {
+                for (int jb = 0; jb < cnt; jb += HP * TPR) {
+                    double t[HP];
+#pragma unroll
+                    for (int u = 0; u < HP; ++u) {
+                        const int j = jb + qd + TPR * u;
+                        t[u] = (base == 0 && jb == 0) ? hpre[u]
+                               : ((j < cnt) ? H[(int64_t)j * cnt + i] : 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < HP; ++u) {
+                        const int j = jb + qd + TPR * u;
+                        if (j < cnt) s = __builtin_fma(t[u], s_r[j], s);
+                    }
+                }
+            }
+            s = group_sum(s, TPR);
+            if (i < cnt && qd == 0) s_y[i] = s;
         }
         __syncthreads();
-        const double *__restrict__ H = p.H + p.hoff[t];
-        for (int i = tid; i < cnt; i += 256) {
-            double y = 0.0;
-            for (int j = 0; j < cnt; ++j) y = __builtin_fma(H[(int64_t)j * cnt + i], s_r[j], y);
-            s_y[i] = y;
-        }
-        __syncthreads();
-    } else if (p.ymode == 1) {
-        for (int i = tid; i < cnt; i += 256) s_y[i] = p.ygiven[i];
+    } else {
+        if (p.ymode == 1)
+            for (int i = tid; i < cnt; i += NT) s_y[i] = p.ygiven[i];
         __syncthreads();
     }
-    if (p.gb && p.ymode != 2 && blockIdx.x == 0) {
+    if (p.gb && upd && blockIdx.x == 0) {
         V *gb = (V *)p.gb;
-        for (int i = tid; i < cnt; i += 256) gb[s_row[i]] -= (V)s_y[i];
+        for (int i = tid; i < cnt; i += NT) {
+            const int64_t row = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : cst + i;
+            gb[row] -= (V)s_y[i];
+        }
     }
 
-    if (p.ymode != 2) {
-        for (int64_t sub = c0; sub < c1; sub += 128) {
+    V yv[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int qq = g + G * r;
+        yv[r] = (upd && qq < cnt) ? (V)s_y[qq] : (V)0;
+    }
+    V pacc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) pacc[r] = (V)0;
+    for (int64_t sub = c0; sub < c1; sub += 128) {
+        const int64_t col = sub + (int64_t)v * VW;
+        if (sub != c0) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                ua[r] = (crow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, col, c1) : zero4;
+                un[r] = (nrow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, col, c1) : zero4;
+            }
+        }
+        if (upd) {
             V acc[VW];
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[e] = (V)0;
-            const int64_t col = sub + (int64_t)v * VW;
-            if (col < c1) {
-                for (int q = g; q < cnt; q += G) {
-                    V a[VW];
-                    load_vec<T, V, AL>(A + s_row[q] * p.ld, col, c1, a);
-                    const V yv = (V)s_y[q];
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) acc[e] = fmaT(a[e], yv, acc[e]);
-                }
+            for (int r = 0; r < RPT; ++r) {
+                V a[VW];
+                cvt_raw<T, V>(ua[r], a);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc[e] = fmaT(a[e], yv[r], acc[e]);
             }
 #pragma unroll
             for (int e = 0; e < VW; ++e) s_red[g][v * VW + e] = acc[e];
@@ -183,114 +267,83 @@ __global__ __launch_bounds__(256) void k_step_dense(StepP p) {
             }
             __syncthreads();
         }
-        for (int c = tid; c < wcols; c += 256) x[c0 + c] = s_x[c];
-    }
-
-    if (p.nxt.kind >= 0) {
-        int64_t nstart;
-        int ncnt, nt;
-        resolve_rows<V>(p.nxt, p.off, p.tau, &nstart, &ncnt, &nt);
-        for (int q = g; q < ncnt; q += G) {
-            const int64_t row = (p.nxt.kind == 1) ? (int64_t)p.nxt.idx[q] : nstart + q;
-            const T *ar = A + row * p.ld;
-            V acc = (V)0;
-            for (int64_t sub = c0; sub < c1; sub += 128) {
-                const int64_t col = sub + (int64_t)v * VW;
-                if (col < c1) {
-                    V a[VW];
-                    load_vec<T, V, AL>(ar, col, c1, a);
+        if (col < c1) {
 #pragma unroll
-                    for (int e = 0; e < VW; ++e)
-                        if (col + e < c1) acc = fmaT(a[e], s_x[col + e - c0], acc);
-                }
+            for (int r = 0; r < RPT; ++r) {
+                V a[VW];
+                cvt_raw<T, V>(un[r], a);
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    if (col + e < c1) pacc[r] = fmaT(a[e], s_x[col + e - c0], pacc[r]);
             }
-            acc = group_sum(acc, NV);
-            if (v == 0) p.Pout[(int64_t)blockIdx.x * p.bmax + q] = (double)acc;
         }
+    }
+    if (upd)
+        for (int c = tid; c < wcols; c += NT) x[c0 + c] = s_x[c];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const V s = group_sum(pacc[r], NV);
+        if (v == 0 && nrow[r] >= 0) p.Pout[(int64_t)blockIdx.x * p.bmax + g + G * r] = (double)s;
     }
 }
 
 // ------------------------------------------------------------ block Gram --
-// Lower triangle of A_S A_S^T over a column range, accumulated in FP64 (the
-// block Gram of the greedy step, Algorithm 1).  A 32-column tile of the rows
-// is staged in LDS transposed ([column][row]); thread t owns one MT x MT
-// micro-tile of the lower triangle of tiles.
-constexpr int GT = 32;  // columns per LDS tile
-
-template <typename T, int MT>
-__device__ __forceinline__ void gram_accumulate(const T *__restrict__ A, int64_t ld,
-                                                const int64_t *rows, int K, int64_t c0,
-                                                int64_t c1, double (&acc)[MT][MT], int bi,
-                                                int bj, double (*At)[MAXB + 8]) {
-#pragma unroll
-    for (int u = 0; u < MT; ++u)
-#pragma unroll
-        for (int w = 0; w < MT; ++w) acc[u][w] = 0.0;
-    for (int64_t cb = c0; cb < c1; cb += GT) {
-        const int tc = (int)((cb + GT < c1) ? GT : (c1 - cb));
-        for (int e = threadIdx.x; e < K * GT; e += blockDim.x) {
-            const int q = e / GT, c = e % GT;
-            At[c][q] = (c < tc) ? (double)to_v<double>(A[rows[q] * ld + cb + c]) : 0.0;
-        }
-        __syncthreads();
-        if (bi >= 0) {
-            for (int c = 0; c < tc; ++c) {
-                double a[MT], bb[MT];
-#pragma unroll
-                for (int u = 0; u < MT; ++u) {
-                    a[u] = At[c][bi * MT + u];
-                    bb[u] = At[c][bj * MT + u];
-                }
-#pragma unroll
-                for (int u = 0; u < MT; ++u)
-#pragma unroll
-                    for (int w = 0; w < MT; ++w) acc[u][w] = __builtin_fma(a[u], bb[w], acc[u][w]);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ void tile_of(int t, int nt, int *bi, int *bj) {
-    // t-th tile of the lower triangle of an nt x nt tile grid, row-major
-    int i = 0, base = 0;
-    while (i < nt && base + i + 1 <= t) { base += i + 1; ++i; }
-    if (i >= nt) { *bi = -1; *bj = -1; return; }
-    *bi = i;
-    *bj = t - base;
-}
-
-template <typename T, int MT>
-__global__ __launch_bounds__(256) void k_gram_dense(const T *__restrict__ A, int64_t ld, int64_t n,
-                                                    const int32_t *__restrict__ idx, int K,
-                                                    int64_t wg, double *__restrict__ Gpart,
-                                                    const Ctrl *__restrict__ ctrl) {
-    if (ctrl->done) return;
-    __shared__ double At[GT][MAXB + 8];
-    __shared__ int64_t rows[MAXB];
-    for (int q = threadIdx.x; q < K; q += blockDim.x) rows[q] = idx[q];
-    for (int e = threadIdx.x; e < GT * (MAXB + 8); e += blockDim.x) (&At[0][0])[e] = 0.0;
-    __syncthreads();
-    const int nt = (K + MT - 1) / MT;
-    int bi = -1, bj = -1;
-    if ((int)threadIdx.x < nt * (nt + 1) / 2) tile_of(threadIdx.x, nt, &bi, &bj);
-    const int64_t c0 = (int64_t)blockIdx.x * wg;
+// Lower triangle of A_S A_S^T (the greedy block's Gram, Algorithm 1) on FP64
+// MFMA: grid x = 16 x 16 tiles of the lower triangle, grid y = column chunks;
+// the four waves of a workgroup take contiguous quarters of the chunk and are
+// summed in wave order.  Output: packed lower partials Gpart[chunk][pk(i,j)].
+template <typename T, bool AL>
+__global__ __launch_bounds__(256) void k_gram_mfma(const T *__restrict__ A, int64_t ld, int64_t n,
+                                                   const int32_t *__restrict__ idx, int K,
+                                                   int64_t wg, double *__restrict__ Gpart,
+                                                   const Ctrl *__restrict__ ctrl) {
+    if (ctrl && ctrl->done) return;
+    constexpr int E = (sizeof(T) == 8) ? 4 : Tr<T>::VW;
+    const int nt = (K + 15) / 16;
+    int bi, bj;
+    tile_of(blockIdx.x, nt, &bi, &bj);
+    const int64_t c0 = (int64_t)blockIdx.y * wg;
     const int64_t c1 = (c0 + wg < n) ? c0 + wg : n;
-    double acc[MT][MT];
-    gram_accumulate<T, MT>(A, ld, rows, K, c0, c1, acc, bi, bj, At);
-    if (bi >= 0) {
-        double *Gp = Gpart + (int64_t)blockIdx.x * K * K;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+    const int64_t stepc = 4 * E;
+    const int64_t span = ((c1 - c0 + 4 * stepc - 1) / (4 * stepc)) * stepc;
+    const int64_t wa = c0 + w * span;
+    const int64_t wb = (wa + span < c1) ? wa + span : c1;
+    const int64_t ra = (bi * 16 + li < K) ? (int64_t)idx[bi * 16 + li] : -1;
+    const int64_t rb = (bj * 16 + li < K) ? (int64_t)idx[bj * 16 + li] : -1;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (wa < wb) mfma_gram_tile<T, AL>(A, ld, ra, rb, wa, wb, acc);
+    __shared__ double red[4][64][4];
 #pragma unroll
-        for (int u = 0; u < MT; ++u)
+    for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
+    __syncthreads();
+    if (w == 0) {
+        const int KP = K * (K + 1) / 2;
 #pragma unroll
-            for (int w = 0; w < MT; ++w) {
-                const int i = bi * MT + u, j = bj * MT + w;
-                if (i < K && j <= i) Gp[i * K + j] = acc[u][w];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const double s = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+            const int ii = bi * 16 + (lane >> 4) + 4 * r, jj = bj * 16 + li;
+            if (ii < K && jj <= ii) Gpart[(int64_t)blockIdx.y * KP + pk(ii, jj)] = s;
+        }
     }
 }
 
 // ------------------------------------------------------------ launchers --
+template <typename T, typename V, bool AL>
+static hipError_t step_launch_rpt(const StepP &p, int nblk, int bmax, hipStream_t s) {
+    constexpr int G = step_groups<T>();
+    const int rpt = (bmax + G - 1) / G;
+    if (rpt <= 3)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 3>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else if (rpt <= 5)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 5>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else if (rpt <= 9)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 9>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 21>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    return hipGetLastError();
+}
+
 template <typename T, typename V>
 static hipError_t step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s) {
     const Layout &L = h->L;
@@ -299,7 +352,8 @@ static hipError_t step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStre
     p.ld = L.ld;
     p.m = L.m;
     p.n = L.n;
-    p.off = h->d_off;
+    p.q = L.q;
+    p.rem = L.rem;
     p.tau = h->d_tau;
     p.cur = a.cur;
     p.ymode = a.ymode;
@@ -307,7 +361,6 @@ static hipError_t step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStre
     p.nch = L.nch_u;
     p.bmax = (int)L.bmax;
     p.H = h->d_H;
-    p.hoff = h->d_hoff;
     p.b = a.b;
     p.x = a.x;
     p.gb = a.gb;
@@ -316,11 +369,8 @@ static hipError_t step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStre
     p.Pout = a.Pout;
     p.wu = L.wu;
     p.ctrl = h->d_ctrl;
-    if (a.aligned)
-        hipLaunchKernelGGL((k_step_dense<T, V, true>), dim3(L.nch_u), dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL((k_step_dense<T, V, false>), dim3(L.nch_u), dim3(256), 0, s, p);
-    return hipGetLastError();
+    if (a.aligned) return step_launch_rpt<T, V, true>(p, L.nch_u, (int)L.bmax, s);
+    return step_launch_rpt<T, V, false>(p, L.nch_u, (int)L.bmax, s);
 }
 
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s) {
@@ -329,19 +379,22 @@ hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStre
     return step_typed<bf16_t, float>(h, a, s);
 }
 
-template <typename T, typename V>
+template <typename T, typename V, int ROWS>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
                               const void *x, double *axp, hipStream_t s) {
     const Layout &L = h->L;
-    const int rpw = 4;
-    const int64_t groups = (L.m + 4 * rpw - 1) / (4 * rpw);
+    // persistent grid: 4 workgroups (16 waves) per CU, fewer for short matrices
+    int64_t groups = (L.m + 4 * ROWS - 1) / (4 * ROWS);
+    const int64_t cap = 4 * (int64_t)h->ncu;
+    if (groups > cap) groups = cap;
     dim3 grid((unsigned)groups, (unsigned)L.nseg);
     if (aligned)
-        hipLaunchKernelGGL((k_resid_dense<T, V, true>), grid, dim3(256), 0, s, (const T *)A, L.ld,
-                           L.m, L.n, (const V *)x, axp, rpw, (const Ctrl *)h->d_ctrl);
+        hipLaunchKernelGGL((k_resid_dense<T, V, true, ROWS>), grid, dim3(256), 0, s, (const T *)A,
+                           L.ld, L.m, L.n, (const V *)x, axp, (const Ctrl *)h->d_ctrl);
     else
-        hipLaunchKernelGGL((k_resid_dense<T, V, false>), grid, dim3(256), 0, s, (const T *)A,
-                           L.ld, L.m, L.n, (const V *)x, axp, rpw, (const Ctrl *)h->d_ctrl);
+        hipLaunchKernelGGL((k_resid_dense<T, V, false, ROWS>), grid, dim3(256), 0, s,
+                           (const T *)A, L.ld, L.m, L.n, (const V *)x, axp,
+                           (const Ctrl *)h->d_ctrl);
     return hipGetLastError();
 }
 
@@ -349,48 +402,49 @@ hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt,
                                  int vec, const void *x, double *axp, hipStream_t s) {
     if (vec == VEC_F64) {
         if (dt != RORBK_F64) return hipErrorInvalidValue;
-        return resid_typed<double, double>(h, A, aligned, x, axp, s);
+        return resid_typed<double, double, 1>(h, A, aligned, x, axp, s);
     }
-    if (dt == RORBK_F32) return resid_typed<float, float>(h, A, aligned, x, axp, s);
-    return resid_typed<bf16_t, float>(h, A, aligned, x, axp, s);
+    if (dt == RORBK_F32) return resid_typed<float, float, 2>(h, A, aligned, x, axp, s);
+    return resid_typed<bf16_t, float, 2>(h, A, aligned, x, axp, s);
 }
 
 template <typename T>
-static hipError_t gram_typed(const rorbk_handle_s *h, const void *A, const int32_t *idx, int K,
-                             double *Gpart, hipStream_t s) {
+static hipError_t gram_typed(const rorbk_handle_s *h, const void *A, int aligned,
+                             const int32_t *idx, int K, double *Gpart, hipStream_t s) {
     const Layout &L = h->L;
-    dim3 grid(L.nch_g);
-    if (K <= 32)
-        hipLaunchKernelGGL((k_gram_dense<T, 2>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
-                           idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
-    else if (K <= 64)
-        hipLaunchKernelGGL((k_gram_dense<T, 4>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
+    const int nt = (K + 15) / 16;
+    dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)L.nch_g);
+    if (aligned)
+        hipLaunchKernelGGL((k_gram_mfma<T, true>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
                            idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
     else
-        hipLaunchKernelGGL((k_gram_dense<T, 8>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
-                           idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
+        hipLaunchKernelGGL((k_gram_mfma<T, false>), grid, dim3(256), 0, s, (const T *)A, L.ld,
+                           L.n, idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt, const int32_t *idx,
                              int K, double *Gpart, hipStream_t s) {
-    if (dt == RORBK_F64) return gram_typed<double>(h, A, idx, K, Gpart, s);
-    if (dt == RORBK_F32) return gram_typed<float>(h, A, idx, K, Gpart, s);
-    return gram_typed<bf16_t>(h, A, idx, K, Gpart, s);
+    const int al = h->aligned;
+    if (dt == RORBK_F64) return gram_typed<double>(h, A, al, idx, K, Gpart, s);
+    if (dt == RORBK_F32) return gram_typed<float>(h, A, al, idx, K, Gpart, s);
+    return gram_typed<bf16_t>(h, A, al, idx, K, Gpart, s);
 }
 
 // ------------------------------------------------------------------ setup --
 // Centroids (Section 2: the sum of a block's rows), FP64: thread per column,
-// rows added in order.  Grid: x = column groups, y = blocks.
+// rows added in order.  Grid: x = blocks, y = column groups.
 template <typename T>
 __global__ __launch_bounds__(256) void k_centroid_dense(const T *__restrict__ A, int64_t ld,
-                                                        int64_t n, const int64_t *__restrict__ off,
+                                                        int64_t n, int64_t q, int64_t rem,
                                                         double *__restrict__ cen) {
     const int64_t t = blockIdx.x;
     const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
     if (c >= n) return;
+    const int64_t r0 = blk_start(t, q, rem);
+    const int bt = blk_rows(t, q, rem);
     double s = 0.0;
-    for (int64_t i = off[t]; i < off[t + 1]; ++i) s += (double)to_v<double>(A[i * ld + c]);
+    for (int i = 0; i < bt; ++i) s += (double)to_v<double>(A[(r0 + i) * ld + c]);
     cen[t * n + c] = s;
 }
 
@@ -404,67 +458,60 @@ __global__ __launch_bounds__(256) void k_rownorm(const double *__restrict__ cen,
     if (threadIdx.x == 0) nrm[blockIdx.x] = sqrt(s);
 }
 
-// Cosine row sums (Section 2, C(i,j) = |<c_i,c_j>| / (|c_i||c_j|)): a 64 x 64
-// tile of the centroid Gram per workgroup (16 x 16 threads, 4 x 4 each, FP64),
-// then for each row t of the tile the sum of its 64 normalised |entries| in
-// column order -> Sp[t][tile].  A zero centroid has C(t,t) = 1 and C(t,j) = 0.
-constexpr int CT = 64;
-__global__ __launch_bounds__(256) void k_cos_tiles(const double *__restrict__ cen, int64_t k,
-                                                   int64_t n, const double *__restrict__ nrm,
-                                                   double *__restrict__ Sp, int64_t ntile) {
-    __shared__ double Ti[16][CT + 1], Tj[16][CT + 1];
-    __shared__ double outt[CT][CT + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int64_t i0 = (int64_t)blockIdx.y * CT, j0 = (int64_t)blockIdx.x * CT;
-    double acc[4][4];
+// Cosine row sums (Section 2, C(i,j) = |<c_i,c_j>| / (|c_i||c_j|)) from the
+// centroid Gram on FP64 MFMA: one 16 x 16 tile of the lower triangle per
+// workgroup (four waves split the columns).  Tile (bi, bj) yields, for each row
+// i of block-row bi, the sum of its 16 normalised |entries| -> Sp[i][bj], and
+// (bi != bj) for each row j of block-row bj the transposed sum -> Sp[j][bi];
+// every Sp entry is written exactly once.  A zero centroid has C(t,t) = 1 and
+// C(t,j) = 0.
+template <bool AL>
+__global__ __launch_bounds__(256) void k_cos_mfma(const double *__restrict__ cen, int64_t k,
+                                                  int64_t n, const double *__restrict__ nrm,
+                                                  double *__restrict__ Sp, int64_t ntc) {
+    int bi, bj;
+    tile_of(blockIdx.x, (int)ntc, &bi, &bj);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+    const int64_t stepc = 16;   // 4 lane groups x 4 columns (FP64)
+    const int64_t span = ((n + 4 * stepc - 1) / (4 * stepc)) * stepc;
+    const int64_t wa = w * span;
+    const int64_t wb = (wa + span < n) ? wa + span : n;
+    const int64_t ra = (bi * 16 + li < k) ? bi * 16 + li : -1;
+    const int64_t rb = (bj * 16 + li < k) ? bj * 16 + li : -1;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (wa < wb) mfma_gram_tile<double, AL>(cen, n, ra, rb, wa, wb, acc);
+    __shared__ double red[4][64][4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
-    for (int64_t cb = 0; cb < n; cb += 16) {
-        for (int e = threadIdx.x; e < 16 * CT; e += 256) {
-            const int r = e / 16, c = e % 16;
-            const int64_t col = cb + c;
-            Ti[c][r] = (i0 + r < k && col < n) ? cen[(i0 + r) * n + col] : 0.0;
-            Tj[c][r] = (j0 + r < k && col < n) ? cen[(j0 + r) * n + col] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int c = 0; c < 16; ++c) {
-            double a[4], bb[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = Ti[c][ty * 4 + u];
-                bb[u] = Tj[c][tx * 4 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w) acc[u][w] = __builtin_fma(a[u], bb[w], acc[u][w]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const int64_t i = i0 + ty * 4 + u, j = j0 + tx * 4 + w;
-            double cij = 0.0;
-            if (i < k && j < k) {
-                const double ni = nrm[i], nj = nrm[j];
-                if (ni == 0.0 || nj == 0.0) cij = (i == j) ? 1.0 : 0.0;
-                else cij = fabs(acc[u][w]) / (ni * nj);
-            }
-            outt[ty * 4 + u][tx * 4 + w] = cij;
-        }
+    for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
     __syncthreads();
-    if (threadIdx.x < CT) {
-        const int64_t i = i0 + threadIdx.x;
-        if (i < k) {
-            double s = 0.0;
-            for (int w = 0; w < CT; ++w) s += outt[threadIdx.x][w];
-            Sp[i * ntile + blockIdx.x] = s;
+    if (w != 0) return;
+    const int64_t jj = (int64_t)bj * 16 + li;
+    double cval[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double d = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+        const int64_t ii = (int64_t)bi * 16 + (lane >> 4) + 4 * r;
+        double c = 0.0;
+        if (ii < k && jj < k) {
+            const double ni = nrm[ii], nj = nrm[jj];
+            if (ni == 0.0 || nj == 0.0) c = (ii == jj) ? 1.0 : 0.0;
+            else c = fabs(d) / (ni * nj);
         }
+        cval[r] = c;
+    }
+    // row sums: the 16 lanes of a lane group hold one row's 16 columns
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double rs = group_sum(cval[r], 16);
+        const int64_t ii = (int64_t)bi * 16 + (lane >> 4) + 4 * r;
+        if (li == 0 && ii < k) Sp[ii * ntc + bj] = rs;
+    }
+    if (bi != bj) {
+        // column sums: registers r, then lane groups (xor 16, 32)
+        double cs = ((cval[0] + cval[1]) + cval[2]) + cval[3];
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (lane < 16 && jj < k) Sp[jj * ntc + bi] = cs;
     }
 }
 
@@ -494,10 +541,16 @@ hipError_t launch_proposal_from_centroids(const rorbk_handle_s *h, double *cen, 
                                           double *Sp, hipStream_t s) {
     const Layout &L = h->L;
     hipLaunchKernelGGL(k_rownorm, dim3((unsigned)L.k), dim3(256), 0, s, cen, L.n, nrm);
-    const int64_t nt = (L.k + CT - 1) / CT;
-    hipLaunchKernelGGL(k_cos_tiles, dim3((unsigned)nt, (unsigned)nt), dim3(256), 0, s, cen, L.k,
-                       L.n, nrm, Sp, nt);
-    hipLaunchKernelGGL(k_proposal, dim3(1), dim3(256), 0, s, Sp, nt, L.k, L.n, h->d_S,
+    const int64_t ntc = (L.k + 15) / 16;
+    const int64_t tiles = ntc * (ntc + 1) / 2;
+    const bool al = (L.n % 2) == 0;   // 16-byte rows of the FP64 centroid matrix
+    if (al)
+        hipLaunchKernelGGL(k_cos_mfma<true>, dim3((unsigned)tiles), dim3(256), 0, s, cen, L.k, L.n,
+                           nrm, Sp, ntc);
+    else
+        hipLaunchKernelGGL(k_cos_mfma<false>, dim3((unsigned)tiles), dim3(256), 0, s, cen, L.k,
+                           L.n, nrm, Sp, ntc);
+    hipLaunchKernelGGL(k_proposal, dim3(1), dim3(256), 0, s, Sp, ntc, L.k, L.n, h->d_S,
                        h->d_pbar, h->d_W);
     return hipGetLastError();
 }
@@ -508,96 +561,178 @@ hipError_t launch_setup_proposal_dense(const rorbk_handle_s *h, const void *A, i
     const Layout &L = h->L;
     double *cen = scratch;                      // k * n
     double *nrm = cen + L.k * L.n;              // k
-    double *Sp = nrm + L.k;                     // k * ntile
+    double *Sp = nrm + L.k;                     // k * ntc
     dim3 grid((unsigned)L.k, (unsigned)((L.n + 255) / 256));
     if (dt == RORBK_F64)
         hipLaunchKernelGGL(k_centroid_dense<double>, grid, dim3(256), 0, s, (const double *)A,
-                           L.ld, L.n, h->d_off, cen);
+                           L.ld, L.n, L.q, L.rem, cen);
     else if (dt == RORBK_F32)
         hipLaunchKernelGGL(k_centroid_dense<float>, grid, dim3(256), 0, s, (const float *)A, L.ld,
-                           L.n, h->d_off, cen);
+                           L.n, L.q, L.rem, cen);
     else
         hipLaunchKernelGGL(k_centroid_dense<bf16_t>, grid, dim3(256), 0, s, (const bf16_t *)A,
-                           L.ld, L.n, h->d_off, cen);
+                           L.ld, L.n, L.q, L.rem, cen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_proposal_from_centroids(h, cen, nrm, Sp, s);
 }
 
-// Stored inverse of each fixed block (Section 3.1 stores the inverse of the
-// regularised block Gram): G_t = A_t A_t^T + lambda I in FP64, its packed
-// Cholesky factor in LDS, then column j of G_t^{-1} by forward and backward
-// substitution (thread j), written row-major (G_t^{-1} is symmetric).
-template <typename T, int MT>
-__global__ __launch_bounds__(256) void k_block_inverse_dense(const T *__restrict__ A, int64_t ld,
-                                                             int64_t n,
-                                                             const int64_t *__restrict__ off,
-                                                             const int64_t *__restrict__ hoff,
-                                                             double lambda, double *__restrict__ H,
-                                                             int32_t *__restrict__ fail) {
-    __shared__ double At[GT][MAXB + 8];
-    __shared__ double Lp[PACKED_MAX];
-    __shared__ int64_t rows[MAXB];
-    const int64_t t = blockIdx.x;
-    const int64_t start = off[t];
-    const int K = (int)(off[t + 1] - start);
-    for (int q = threadIdx.x; q < K; q += blockDim.x) rows[q] = start + q;
-    for (int e = threadIdx.x; e < GT * (MAXB + 8); e += blockDim.x) (&At[0][0])[e] = 0.0;
+// Fixed-block Grams G_t = A_t A_t^T on FP64 MFMA (Section 3.1 stores each
+// block's regularised inverse once): grid x = lower 16 x 16 tiles of the
+// largest block, grid y = blocks; packed lower output Gs[t][pk(i,j)].
+template <typename T, bool AL>
+__global__ __launch_bounds__(256) void k_block_gram_mfma(const T *__restrict__ A, int64_t ld,
+                                                         int64_t n, int64_t q, int64_t rem,
+                                                         int64_t kpmax, double *__restrict__ Gs) {
+    const int64_t t = blockIdx.y;
+    const int bt = blk_rows(t, q, rem);
+    const int64_t r0 = blk_start(t, q, rem);
+    const int nt = (bt + 15) / 16;
+    int bi, bj;
+    tile_of(blockIdx.x, (int)((q + 1 + 15) / 16), &bi, &bj);
+    if (bi < 0 || bi >= nt || bj >= nt) return;
+    constexpr int E = (sizeof(T) == 8) ? 4 : Tr<T>::VW;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+    const int64_t stepc = 4 * E;
+    const int64_t span = ((n + 4 * stepc - 1) / (4 * stepc)) * stepc;
+    const int64_t wa = w * span;
+    const int64_t wb = (wa + span < n) ? wa + span : n;
+    const int64_t ra = (bi * 16 + li < bt) ? r0 + bi * 16 + li : -1;
+    const int64_t rb = (bj * 16 + li < bt) ? r0 + bj * 16 + li : -1;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (wa < wb) mfma_gram_tile<T, AL>(A, ld, ra, rb, wa, wb, acc);
+    __shared__ double red[4][64][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
     __syncthreads();
-    const int nt = (K + MT - 1) / MT;
-    int bi = -1, bj = -1;
-    if ((int)threadIdx.x < nt * (nt + 1) / 2) tile_of(threadIdx.x, nt, &bi, &bj);
-    double acc[MT][MT];
-    gram_accumulate<T, MT>(A, ld, rows, K, 0, n, acc, bi, bj, At);
-    if (bi >= 0) {
+    if (w == 0) {
 #pragma unroll
-        for (int u = 0; u < MT; ++u)
-#pragma unroll
-            for (int w = 0; w < MT; ++w) {
-                const int i = bi * MT + u, j = bj * MT + w;
-                if (i < K && j <= i) Lp[pk(i, j)] = acc[u][w] + (i == j ? lambda : 0.0);
-            }
+        for (int r = 0; r < 4; ++r) {
+            const double s = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
+            const int ii = bi * 16 + (lane >> 4) + 4 * r, jj = bj * 16 + li;
+            if (ii < bt && jj <= ii) Gs[t * kpmax + pk(ii, jj)] = s;
+        }
     }
+}
+
+// Stored inverse of each fixed block: (G_t + lambda I)^{-1} from the LDL^T
+// factor (LDS), column j by thread j (forward with unit L, scale by D^{-1},
+// backward with L^T), written row-major (the inverse is symmetric).
+template <int MT>
+__global__ __launch_bounds__(256) void k_block_inverse(const double *__restrict__ Gs, int64_t kpmax,
+                                                       int64_t q, int64_t rem, double lambda,
+                                                       double *__restrict__ H,
+                                                       int32_t *__restrict__ fail) {
+    __shared__ double Gp[PACKED_MAX];
+    __shared__ double z[MAXB];
+    __shared__ double colbuf[2 * MAXB];
+    __shared__ double invd[MAXB];
+    const int64_t t = blockIdx.x;
+    const int K = blk_rows(t, q, rem);
+    const int KP = K * (K + 1) / 2;
+    for (int f = threadIdx.x; f < KP; f += blockDim.x) Gp[f] = Gs[t * kpmax + f];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) z[i] = 0.0;
     __syncthreads();
-    if (!chol_packed(Lp, K)) {
+    for (int i = threadIdx.x; i < K; i += blockDim.x) Gp[pk(i, i)] += lambda;
+    __syncthreads();
+    if (!ldl_solve<MT>(Gp, z, K, colbuf)) {
         if (threadIdx.x == 0) *fail = 1;
         return;
     }
-    double *Hb = H + hoff[t];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) invd[i] = 1.0 / Gp[pk(i, i)];
+    __syncthreads();
+    double *Hb = H + blk_hoff(t, q, rem);
     for (int j = threadIdx.x; j < K; j += blockDim.x) {
         double *h = Hb + (int64_t)j * K;
-        for (int i = 0; i < K; ++i) {  // L z = e_j
-            if (i < j) { h[i] = 0.0; continue; }
+        for (int i = 0; i < j; ++i) h[i] = 0.0;
+        for (int i = j; i < K; ++i) {          // unit lower: z_i = e_j - sum l_ip z_p
             double s = (i == j) ? 1.0 : 0.0;
-            for (int q = j; q < i; ++q) s -= Lp[pk(i, q)] * h[q];
-            h[i] = s / Lp[pk(i, i)];
+            for (int p2 = j; p2 < i; ++p2) s -= Gp[pk(i, p2)] * invd[p2] * h[p2];
+            h[i] = s;
         }
-        for (int i = K - 1; i >= 0; --i) {  // L^T h = z
+        for (int i = j; i < K; ++i) h[i] *= invd[i];
+        for (int i = K - 1; i >= 0; --i) {     // L^T h = D^{-1} z
             double s = h[i];
-            for (int q = i + 1; q < K; ++q) s -= Lp[pk(q, i)] * h[q];
-            h[i] = s / Lp[pk(i, i)];
+            for (int p2 = i + 1; p2 < K; ++p2) s -= Gp[pk(p2, i)] * invd[i] * h[p2];
+            h[i] = s;
         }
+    }
+}
+
+// Same for blocks of at most 64 rows on one wave: LDL^T in registers
+// (ldl_wave64), then column j of the inverse by lane j from the factor.
+__global__ __launch_bounds__(64) void k_block_inverse64(const double *__restrict__ Gs,
+                                                        int64_t kpmax, int64_t q, int64_t rem,
+                                                        double lambda, double *__restrict__ H,
+                                                        int32_t *__restrict__ fail) {
+    __shared__ double Gp[64 * 65 / 2];
+    __shared__ double z[64];
+    __shared__ double colbuf[128];
+    __shared__ double Lc[64 * 65];
+    const int64_t t = blockIdx.x;
+    const int K = blk_rows(t, q, rem);
+    const int KP = K * (K + 1) / 2;
+    const int lane = threadIdx.x;
+    for (int f = lane; f < KP; f += 64) Gp[f] = Gs[t * kpmax + f];
+    z[lane] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < K) Gp[pk(lane, lane)] += lambda;
+    __builtin_amdgcn_wave_barrier();
+    if (!ldl_wave64(Gp, z, K, colbuf, Lc)) {
+        if (lane == 0) *fail = 1;
+        return;
+    }
+    if (lane >= K) return;
+    const int j = lane;
+    double *h = H + blk_hoff(t, q, rem) + (int64_t)j * K;
+    for (int i = 0; i < j; ++i) h[i] = 0.0;
+    for (int i = j; i < K; ++i) {            // unit lower: z_i = e_j - sum l_ip z_p
+        double sacc = (i == j) ? 1.0 : 0.0;
+        for (int p2 = j; p2 < i; ++p2) sacc -= Lc[p2 * 65 + i] * h[p2];
+        h[i] = sacc;
+    }
+    for (int i = j; i < K; ++i) h[i] /= Lc[i * 65 + i];
+    for (int i = K - 1; i >= 0; --i) {       // L^T h = D^{-1} z
+        double sacc = h[i];
+        for (int p2 = i + 1; p2 < K; ++p2) sacc -= Lc[i * 65 + p2] * h[p2];
+        h[i] = sacc;
     }
 }
 
 hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A, int dt, int aligned,
                                        int32_t *d_fail, hipStream_t s) {
-    (void)aligned;
     const Layout &L = h->L;
-    const int K = (int)L.bmax;
-    dim3 grid((unsigned)L.k);
-#define RORBK_INV(T, MT)                                                                    \
-    hipLaunchKernelGGL((k_block_inverse_dense<T, MT>), grid, dim3(256), 0, s, (const T *)A, \
-                       L.ld, L.n, h->d_off, h->d_hoff, h->lambda, h->d_H, d_fail)
-    if (dt == RORBK_F64) {
-        if (K <= 32) RORBK_INV(double, 2); else if (K <= 64) RORBK_INV(double, 4); else RORBK_INV(double, 8);
-    } else if (dt == RORBK_F32) {
-        if (K <= 32) RORBK_INV(float, 2); else if (K <= 64) RORBK_INV(float, 4); else RORBK_INV(float, 8);
-    } else {
-        if (K <= 32) RORBK_INV(bf16_t, 2); else if (K <= 64) RORBK_INV(bf16_t, 4); else RORBK_INV(bf16_t, 8);
+    const int64_t kp = L.bmax * (L.bmax + 1) / 2;
+    double *Gs = nullptr;
+    hipError_t e = hipMallocAsync((void **)&Gs, sizeof(double) * (size_t)(kp * L.k), s);
+    if (e != hipSuccess) return e;
+    const int nt = (int)((L.bmax + 15) / 16);
+    dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)L.k);
+#define RORBK_BG(T)                                                                             \
+    do {                                                                                        \
+        if (aligned)                                                                            \
+            hipLaunchKernelGGL((k_block_gram_mfma<T, true>), grid, dim3(256), 0, s,             \
+                               (const T *)A, L.ld, L.n, L.q, L.rem, kp, Gs);                    \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_block_gram_mfma<T, false>), grid, dim3(256), 0, s,            \
+                               (const T *)A, L.ld, L.n, L.q, L.rem, kp, Gs);                    \
+    } while (0)
+    if (dt == RORBK_F64) RORBK_BG(double);
+    else if (dt == RORBK_F32) RORBK_BG(float);
+    else RORBK_BG(bf16_t);
+#undef RORBK_BG
+    e = hipGetLastError();
+    if (e == hipSuccess) {
+        if (L.bmax <= 64)
+            hipLaunchKernelGGL(k_block_inverse64, dim3((unsigned)L.k), dim3(64), 0, s, Gs, kp,
+                               L.q, L.rem, h->lambda, h->d_H, d_fail);
+        else
+            hipLaunchKernelGGL(k_block_inverse<8>, dim3((unsigned)L.k), dim3(256), 0, s, Gs, kp,
+                               L.q, L.rem, h->lambda, h->d_H, d_fail);
+        e = hipGetLastError();
     }
-#undef RORBK_INV
-    return hipGetLastError();
+    hipError_t e2 = hipFreeAsync(Gs, s);
+    return e != hipSuccess ? e : e2;
 }
 
 }  // namespace rorbk

@@ -77,9 +77,9 @@ void plan_layout(Layout &L) {
         if (per > 8) per = 8;
         L.wu = 128 * per;
         L.nch_u = (int32_t)((n + L.wu - 1) / L.wu);
-        const int64_t cap = (L.K <= 64) ? 64 : 32;
-        int64_t nch = (n + 63) / 64;
-        if (nch > cap) nch = cap;
+        // greedy Gram: about 256 columns per workgroup, at most 64 chunks
+        int64_t nch = (n + 255) / 256;
+        if (nch > 64) nch = 64;
         if (nch < 1) nch = 1;
         int64_t wg = (n + nch - 1) / nch;
         wg = ((wg + 31) / 32) * 32;
@@ -147,6 +147,9 @@ void destroy_all(rorbk_handle_s *h) {
     free_solve_buffers(h);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (h->evr[i][j]) (void)hipEventDestroy(h->evr[i][j]);
 }
 
 // ----------------------------------------------------------- dispatch ----
@@ -233,6 +236,16 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     ping ^= 1;
 
     const int64_t poll = 16;
+    int timed_slot[2] = {0, 0};
+    auto take_time = [&](int slot) -> int {
+        if (!timed_slot[slot]) return RORBK_OK;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->evr[slot][0], h->evr[slot][1]));
+        h->prof_in_ms += ms;
+        h->prof_in_n += 1;
+        timed_slot[slot] = 0;
+        return RORBK_OK;
+    };
     Ctrl *slots = h->h_ctrl + 1;  // two pinned slots after the mirror
     hipEvent_t evs[2] = {h->ev0, h->ev1};
     int64_t chunk = 0;
@@ -259,7 +272,13 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
             HIPCHK(step(h, a));
             if (l < 2) ping ^= 1;
         }
+        const bool timed = h->profile && ((it - it0) % poll) == 0;
+        if (timed) HIPCHK(hipEventRecord(h->evr[chunk & 1][0], s));
         HIPCHK(residual(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_axp));
+        if (timed) {
+            HIPCHK(hipEventRecord(h->evr[chunk & 1][1], s));
+            timed_slot[chunk & 1] = 1;
+        }
         SelectArgs sa;
         memset(&sa, 0, sizeof(sa));
         sa.vec = o.vec;
@@ -304,6 +323,7 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
                 const int prev = slot ^ 1;
                 HIPCHK(hipEventSynchronize(evs[prev]));
                 if (slots[prev].done) done = true;
+                CHK(take_time(prev));
             }
             ++chunk;
             if (done) break;
@@ -311,6 +331,8 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     }
     HIPCHK(hipMemcpyAsync(h->h_ctrl, h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    CHK(take_time(0));
+    CHK(take_time(1));
     const Ctrl &c = *h->h_ctrl;
     if (c.status != RORBK_OK)
         return fail(c.status, c.status == RORBK_ERR_NONFINITE
@@ -429,6 +451,14 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     h->aligned64 = (h->A64 && aligned16(h->A64, L.ld, 8)) ? 1 : 0;
     h->refine_inner = 50;
     h->refine_eta = 1e-4;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu <= 0)
+            ncu = 256;
+        h->ncu = ncu;
+    }
 
     const int64_t k = L.k, K = L.K, bmax = L.bmax;
     const int64_t q = L.q, rem = L.rem;
@@ -468,7 +498,7 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_I, bmax);
     ALLOC(h->d_rI, bmax);
     ALLOC(h->d_y, bmax);
-    ALLOC(h->d_G, (int64_t)L.nch_g * K * K);
+    ALLOC(h->d_G, (int64_t)L.nch_g * K * (K + 1) / 2);
     ALLOC(h->d_red, 64);
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_ctrl, 3 * sizeof(Ctrl), hipHostMallocDefault);
@@ -478,7 +508,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return fail(RORBK_ERR_OOM, "pinned allocation failed: %s", hipGetErrorString(e));
     }
     memset(h->h_ctrl, 0, 3 * sizeof(Ctrl));
-    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipEventCreate(&h->evr[0][0]) != hipSuccess || hipEventCreate(&h->evr[0][1]) != hipSuccess ||
+        hipEventCreate(&h->evr[1][0]) != hipSuccess || hipEventCreate(&h->evr[1][1]) != hipSuccess) {
         destroy_all(h);
         delete h;
         return fail(RORBK_ERR_HIP, "event creation failed");
@@ -494,7 +526,7 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return bail(fail(RORBK_ERR_HIP, "partition launch failed"));
     // centroid cosines and the proposal
     {
-        const int64_t ntile = (k + 63) / 64;
+        const int64_t ntile = (k + 15) / 16;
         const int64_t len = k * L.n + k + k * ntile;
         double *scratch = nullptr;
         rc = dalloc(&scratch, (size_t)len);
@@ -674,6 +706,15 @@ int ror_bk_set_replay(rorbk_handle h, const int32_t *tau_host, const int32_t *I_
     return RORBK_OK;
 }
 
+int ror_bk_get_profile(rorbk_handle h, double *out4_host) {
+    if (!h || !out4_host) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
+    out4_host[0] = h->prof_in_n ? h->prof_in_ms / (double)h->prof_in_n : 0.0;
+    out4_host[1] = (double)h->prof_in_n;
+    out4_host[2] = h->prof_out_n ? h->prof_out_ms / (double)h->prof_out_n : 0.0;
+    out4_host[3] = (double)h->prof_out_n;
+    return RORBK_OK;
+}
+
 int ror_bk_set_refine(rorbk_handle h, int64_t inner_iters, double eta) {
     if (!h || inner_iters < 1 || !(eta >= 0.0) || !std::isfinite(eta))
         return fail(RORBK_ERR_INVALID_ARG, "bad refinement arguments");
@@ -706,7 +747,7 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
     if (max_iters < 0 || start_iter < 0)
         return fail(RORBK_ERR_INVALID_ARG, "max_iters and start_iter must be >= 0");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RORBK_ERR_INVALID_ARG, "tol must be finite, >= 0");
-    if (flags & ~(RORBK_REFINE | RORBK_RECORD | RORBK_REPLAY | RORBK_CHECKPOINT))
+    if (flags & ~(RORBK_REFINE | RORBK_RECORD | RORBK_REPLAY | RORBK_CHECKPOINT | RORBK_PROFILE))
         return fail(RORBK_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     const bool refine = flags & RORBK_REFINE, record = flags & RORBK_RECORD;
     const bool replay = flags & RORBK_REPLAY, ckpt = flags & RORBK_CHECKPOINT;
@@ -726,6 +767,9 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
     inf.rrn = NAN;
     h->rec_valid = 0;
     h->rec_iters = 0;
+    h->profile = (flags & RORBK_PROFILE) ? 1 : 0;
+    h->prof_in_ms = h->prof_out_ms = 0.0;
+    h->prof_in_n = h->prof_out_n = 0;
     if (max_iters == 0) {
         if (info) *info = inf;
         return RORBK_OK;
@@ -798,7 +842,9 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
         bool conv = false;
         for (;;) {
             HIPCHK(launch_init_ctrl(h->d_ctrl, tol, h->d_red + 1, s));
+            if (h->profile) HIPCHK(hipEventRecord(h->evr[0][0], s));
             HIPCHK(residual(h, h->A64, RORBK_F64, h->aligned64, VEC_F64, x, h->d_axp));
+            if (h->profile) HIPCHK(hipEventRecord(h->evr[0][1], s));
             SelectArgs sa;
             memset(&sa, 0, sizeof(sa));
             sa.vec = VEC_F64;
@@ -810,6 +856,12 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
             HIPCHK(launch_select(h, sa, s));
             HIPCHK(hipMemcpyAsync(&h->h_ctrl[0], h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            if (h->profile) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, h->evr[0][0], h->evr[0][1]));
+                h->prof_out_ms += ms;
+                h->prof_out_n += 1;
+            }
             const Ctrl c = h->h_ctrl[0];
             if (c.status) {
                 rc = fail(c.status, "non-finite FP64 residual");

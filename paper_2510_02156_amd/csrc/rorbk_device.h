@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "rorbk_internal.h"
 
 namespace rorbk {
@@ -18,6 +20,21 @@ typedef uint16_t bf16_t;
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef uint32_t uvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+// Closed-form partition (Algorithm 1, first step): block t starts at
+// t*q + min(t, rem) and has q or q+1 rows; its stored inverse starts at
+// sum_{s<t} b_s^2.
+__device__ __forceinline__ int64_t blk_start(int64_t t, int64_t q, int64_t rem) {
+    return t * q + (t < rem ? t : rem);
+}
+__device__ __forceinline__ int blk_rows(int64_t t, int64_t q, int64_t rem) {
+    return (int)(q + (t < rem ? 1 : 0));
+}
+__device__ __forceinline__ int64_t blk_hoff(int64_t t, int64_t q, int64_t rem) {
+    const int64_t big = t < rem ? t : rem;
+    return big * (q + 1) * (q + 1) + (t - big) * q * q;
+}
 
 // Storage traits: elements per 16-byte load.
 template <typename T> struct Tr;
@@ -96,6 +113,101 @@ __device__ __forceinline__ void load_vec_nt(const T *__restrict__ row, int64_t c
     }
 }
 
+// 16 raw bytes (VW elements) of a row at column c; elements at or past `lim`
+// read as zero.  ALIGNED as for load_vec.
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ uvec4 load_raw(const T *__restrict__ row, int64_t c, int64_t lim) {
+    constexpr int VW = Tr<T>::VW;
+    if (ALIGNED && c + VW <= lim) return *reinterpret_cast<const uvec4 *>(row + c);
+    uvec4 w = {0u, 0u, 0u, 0u};
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (c + e < lim) {
+                const uint64_t u = (uint64_t)__double_as_longlong((double)row[c + e]);
+                w[2 * e] = (uint32_t)u;
+                w[2 * e + 1] = (uint32_t)(u >> 32);
+            }
+    } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (c + e < lim) w[e] = __float_as_uint((float)row[c + e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (c + e < lim) w[e >> 1] |= ((uint32_t)(uint16_t)row[c + e]) << (16 * (e & 1));
+    }
+    return w;
+}
+
+template <typename T, typename V>
+__device__ __forceinline__ void cvt_raw(const uvec4 &w, V (&out)[Tr<T>::VW]) {
+    if constexpr (sizeof(T) == 8) {
+        out[0] = (V)__longlong_as_double((long long)(((uint64_t)w[1] << 32) | w[0]));
+        out[1] = (V)__longlong_as_double((long long)(((uint64_t)w[3] << 32) | w[2]));
+    } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = (V)__uint_as_float(w[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            out[2 * e] = (V)__uint_as_float(w[e] << 16);
+            out[2 * e + 1] = (V)__uint_as_float(w[e] & 0xffff0000u);
+        }
+    }
+}
+
+// FP64 MFMA tile of a Gram product: acc += X_a X_b^T over columns [c0, c1)
+// for a 16 x 16 tile, one wave.  Lane l supplies row ra (A side) and rb (B
+// side) for tile row/column l % 16 (a negative row reads as zero) and the
+// E = 32 / sizeof(T) >= 4 consecutive columns c + g*E .. of lane group
+// g = l / 16, which serve as the k index of E v_mfma_f64_16x16x4f64 steps
+// (the sum runs over every column once, in a fixed order).  Result layout:
+// D[i][j] sits in register i / 4 of lane (i % 4) * 16 + j.  c0 must be a
+// multiple of E when ALIGNED.
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void mfma_gram_tile(const T *__restrict__ X, int64_t ld, int64_t ra,
+                                               int64_t rb, int64_t c0, int64_t c1, dvec4 &acc) {
+    constexpr int VW = Tr<T>::VW;
+    constexpr int E = (sizeof(T) == 8) ? 4 : VW;   // columns per lane per macro step
+    constexpr int NL = E / VW;                      // 16-byte loads per row per step
+    constexpr int U = 4;                            // macro steps in flight
+    const int g = (threadIdx.x & 63) >> 4;
+    const T *pa = X + (ra >= 0 ? ra : 0) * ld;
+    const T *pb = X + (rb >= 0 ? rb : 0) * ld;
+    const bool same = (ra == rb);
+    for (int64_t c = c0; c < c1; c += 4 * E * U) {
+        uvec4 wa[U][NL], wb[U][NL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t col = c + (int64_t)u * 4 * E + (int64_t)g * E;
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                const uvec4 z = {0u, 0u, 0u, 0u};
+                wa[u][h] = (ra >= 0 && col + h * VW < c1) ? load_raw<T, ALIGNED>(pa, col + h * VW, c1) : z;
+                wb[u][h] = (!same && rb >= 0 && col + h * VW < c1)
+                               ? load_raw<T, ALIGNED>(pb, col + h * VW, c1) : z;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                double av[VW], bv[VW];
+                cvt_raw<T, double>(wa[u][h], av);
+                if (same) {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) bv[e] = av[e];
+                } else {
+                    cvt_raw<T, double>(wb[u][h], bv);
+                }
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[e], bv[e], acc, 0, 0, 0);
+            }
+    }
+}
+
 // Butterfly sum over the `width` lanes of a lane group (width a power of two
 // <= 64).  The combination order is fixed, so the result is reproducible.
 template <typename V>
@@ -122,97 +234,187 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 __device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
-// In-place Cholesky of a packed lower K x K matrix in LDS by the whole
-// workgroup, one barrier per elimination step.  Step k updates the trailing
-// triangle with the unscaled pivot column (G_ij -= G_ik G_jk / G_kk); the
-// columns are scaled by 1/sqrt(pivot) at the end.  Returns false (uniformly)
-// if a pivot is not positive.
-__device__ inline bool chol_packed(double *Lp, int K) {
+// t-th tile of the lower triangle of an nt x nt tile grid, row-major.
+__device__ __forceinline__ void tile_of(int t, int nt, int *bi, int *bj) {
+    int i = 0, base = 0;
+    while (i < nt && base + i + 1 <= t) { base += i + 1; ++i; }
+    if (i >= nt) { *bi = -1; *bj = -1; return; }
+    *bi = i;
+    *bj = t - base;
+}
+
+// Symmetric positive definite solve (G + diag) y = r for K <= MAXB in one
+// workgroup of 256 threads, G given packed lower in LDS (Gp, overwritten),
+// r in LDS (z, overwritten by y).  Factorisation G = L D L^T (unit L) by
+// right-looking elimination: thread t keeps one MT x MT tile of the lower
+// triangle in registers; at step k the owners of column k publish it to LDS
+// (double-buffered), and after one barrier everyone applies the rank-1 update
+// a_ij -= g_ik g_jk / d_k, which also carries the right-hand side through the
+// forward substitution.  Column k is kept in Gp (unscaled) for the backward
+// substitution y_k = z_k / d_k - sum_{i>k} (g_ik / d_k) y_i, run by wave 0.
+// Returns false (uniformly) if a pivot d_k is not positive.
+template <int MT>
+__device__ bool ldl_solve(double *Gp, double *z, int K, double *colbuf /* 2*MAXB */) {
     __shared__ int s_bad;
+    const int nt = (K + MT - 1) / MT;
+    int bi = -1, bj = -1;
+    if ((int)threadIdx.x < nt * (nt + 1) / 2) tile_of(threadIdx.x, nt, &bi, &bj);
+    double a[MT][MT];
+#pragma unroll
+    for (int u = 0; u < MT; ++u)
+#pragma unroll
+        for (int v = 0; v < MT; ++v) {
+            const int i = bi * MT + u, j = bj * MT + v;
+            a[u][v] = (bi >= 0 && i < K && j <= i) ? Gp[pk(i, j)] : 0.0;
+        }
     if (threadIdx.x == 0) s_bad = 0;
+    // column 0 comes straight from Gp
+    for (int i = threadIdx.x; i < K; i += blockDim.x) colbuf[i] = Gp[pk(i, 0)];
     __syncthreads();
     for (int k = 0; k < K; ++k) {
-        const double d = Lp[pk(k, k)];
+        const double *col = colbuf + (k & 1) * MAXB;
+        double *nxt = colbuf + ((k + 1) & 1) * MAXB;
+        const double d = col[k];
         if (!(d > 0.0)) {
             if (threadIdx.x == 0) s_bad = 1;
             break;  // uniform: every thread reads the same pivot
         }
         const double inv = 1.0 / d;
-        const int w = K - k - 1;
-        const int tot = w * (w + 1) / 2;
-        for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-            // f -> (a, b) with b <= a < w, row-major over the packed triangle
-            int a = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
-            while (a * (a + 1) / 2 > f) --a;
-            while ((a + 1) * (a + 2) / 2 <= f) ++a;
-            const int b = f - a * (a + 1) / 2;
-            const int i = k + 1 + a, j = k + 1 + b;
-            Lp[pk(i, j)] -= Lp[pk(i, k)] * (Lp[pk(j, k)] * inv);
+        // right-hand side (forward substitution with unit L)
+        const double zk = z[k];
+        if (bi >= 0) {
+            double ci[MT], cj[MT];
+#pragma unroll
+            for (int u = 0; u < MT; ++u) {
+                const int i = bi * MT + u, j = bj * MT + u;
+                ci[u] = (i > k && i < K) ? col[i] : 0.0;
+                cj[u] = (j > k && j < K) ? col[j] * inv : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < MT; ++u)
+#pragma unroll
+                for (int v = 0; v < MT; ++v) a[u][v] = __builtin_fma(-ci[u], cj[v], a[u][v]);
+            // publish column k+1 (owners: tiles whose column block holds k+1)
+            const int kk = k + 1;
+            if (kk < K && kk / MT == bj) {
+#pragma unroll
+                for (int u = 0; u < MT; ++u) {
+                    const int i = bi * MT + u;
+#pragma unroll
+                    for (int v = 0; v < MT; ++v)
+                        if (bj * MT + v == kk && i >= kk && i < K) nxt[i] = a[u][v];
+                }
+            }
+        }
+        // keep column k (unscaled) for the backward pass; update z
+        for (int i = k + threadIdx.x; i < K; i += blockDim.x) {
+            Gp[pk(i, k)] = col[i];
+            if (i > k) z[i] = __builtin_fma(-col[i] * inv, zk, z[i]);
         }
         __syncthreads();
     }
     __syncthreads();
-    const bool bad = s_bad != 0;
-    if (bad) return false;
-    // scale: L_ik = G_ik / sqrt(d_k) for i >= k
-    const int tot = K * (K + 1) / 2;
-    for (int f = threadIdx.x; f < tot; f += blockDim.x) {
-        int i = (int)((sqrtf(8.0f * (float)f + 1.0f) - 1.0f) * 0.5f);
-        while (i * (i + 1) / 2 > f) --i;
-        while ((i + 1) * (i + 2) / 2 <= f) ++i;
-        const int k = f - i * (i + 1) / 2;
-        const double dk = Lp[pk(k, k)];
-        // the diagonal is rewritten last, after every column entry has used it
-        if (i != k) Lp[f] = Lp[f] / sqrt(dk);
+    if (s_bad) return false;
+    // backward: y_k = z_k / d_k - sum_{i>k} (g_ik / d_k) y_i, column oriented
+    if (threadIdx.x < WAVE) {
+        const int lane = threadIdx.x;
+        double w[3], invd[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int i = lane + 64 * s;
+            invd[s] = (i < K) ? 1.0 / Gp[pk(i, i)] : 0.0;
+            w[s] = (i < K) ? z[i] * invd[s] : 0.0;
+        }
+        for (int k = K - 1; k >= 0; --k) {
+            const int s = k >> 6, src = k & 63;
+            double yk = (s == 0) ? w[0] : (s == 1 ? w[1] : w[2]);
+            yk = __shfl(yk, src, WAVE);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int i = lane + 64 * t;
+                if (i < k) w[t] = __builtin_fma(-Gp[pk(k, i)] * invd[t], yk, w[t]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int i = lane + 64 * s;
+            if (i < K) z[i] = w[s];
+        }
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < K; k += blockDim.x) Lp[pk(k, k)] = sqrt(Lp[pk(k, k)]);
     __syncthreads();
     return true;
 }
 
-// y = (L L^T)^{-1} r with L packed lower in LDS; done by wave 0 (lane p holds
-// entries p, p+64, p+128), no barriers inside.  r and y live in LDS (may alias).
-__device__ inline void chol_solve_wave(const double *Lp, int K, const double *r, double *y) {
-    if (threadIdx.x >= WAVE) return;
-    const int lane = threadIdx.x;
-    double v[3];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const int i = lane + 64 * s;
-        v[s] = (i < K) ? r[i] : 0.0;
+// Broadcast lane `src` (wave-uniform) of a double to the whole wave.
+__device__ __forceinline__ double bcast64(double v, int src) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Single-wave solve (G) y = r for K <= 64, the workgroup's other waves having
+// left (no block barrier inside).  LDL^T with unit L by right-looking
+// elimination: lane i keeps row i of G in registers (entries j <= i are live).
+// At step k the pivot d_k comes from lane k by readlane, lane i forms
+// l_ik = g_ik / d_k, updates its row g_ij -= l_ik g_jk (j > k) with column k
+// read from LDS, and the forward substitution z_i -= l_ik z_k.  Column k+1 is
+// published to LDS right after its own update, so the write overlaps the rest
+// of the step.  The factor (l_ik below the diagonal, d_k on it) is kept column
+// by column in Lc[k * 65 + i] for the backward pass y_k = z_k / d_k -
+// sum_{i>k} l_ik y_i.  The steps are generated with compile-time k so that
+// every register index is static.
+template <int k>
+__device__ __forceinline__ bool ldl_step64(double (&a)[64], double &zi, int K, int lane,
+                                           double *colbuf, double *Lc) {
+    if (k >= K) return true;
+    const double *col = colbuf + (k & 1) * 64;
+    double *nxt = colbuf + ((k + 1) & 1) * 64;
+    const double d = bcast64(a[k], k);
+    if (!(d > 0.0)) return false;
+    const double inv = 1.0 / d;
+    const double c = a[k] * inv;
+    const double zk = bcast64(zi, k);
+    if (lane > k) zi = __builtin_fma(-c, zk, zi);
+    Lc[k * 65 + lane] = (lane > k) ? c : d;
+    if constexpr (k + 1 < 64) {
+        if (k + 1 < K) a[k + 1] = __builtin_fma(-c, col[k + 1], a[k + 1]);
+        nxt[lane] = a[k + 1];
     }
-    // forward: L z = r
-    for (int j = 0; j < K; ++j) {
-        const int s = j >> 6, src = j & 63;
-        double vj = (s == 0) ? v[0] : (s == 1 ? v[1] : v[2]);
-        vj = __shfl(vj, src, WAVE);
-        const double zj = vj / Lp[pk(j, j)];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int i = lane + 64 * t;
-            if (i > j && i < K) v[t] -= Lp[pk(i, j)] * zj;
-            if (i == j) v[t] = zj;
-        }
-    }
-    // backward: L^T y = z
-    for (int j = K - 1; j >= 0; --j) {
-        const int s = j >> 6, src = j & 63;
-        double vj = (s == 0) ? v[0] : (s == 1 ? v[1] : v[2]);
-        vj = __shfl(vj, src, WAVE);
-        const double yj = vj / Lp[pk(j, j)];
+    for (int j = k + 2; j < 64; ++j)
+        if (j < K) a[j] = __builtin_fma(-c, col[j], a[j]);
+    __builtin_amdgcn_wave_barrier();
+    return true;
+}
+
+template <int... Ks>
+__device__ __forceinline__ bool ldl_steps64(std::integer_sequence<int, Ks...>, double (&a)[64],
+                                            double &zi, int K, int lane, double *colbuf,
+                                            double *Lc) {
+    return (ldl_step64<Ks>(a, zi, K, lane, colbuf, Lc) && ...);
+}
+
+__device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
+                                  double *Lc /* 64*65 */) {
+    const int lane = threadIdx.x & 63;
+    double a[64];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int i = lane + 64 * t;
-            if (i < j) v[t] -= Lp[pk(j, i)] * yj;
-            if (i == j) v[t] = yj;
-        }
+    for (int j = 0; j < 64; ++j) a[j] = (j <= lane && lane < K) ? Gp[pk(lane, j)] : 0.0;
+    double zi = (lane < K) ? z[lane] : 0.0;
+    colbuf[lane] = a[0];
+    __builtin_amdgcn_wave_barrier();
+    if (!ldl_steps64(std::make_integer_sequence<int, 64>{}, a, zi, K, lane, colbuf, Lc))
+        return false;
+    // backward substitution, column oriented
+    double w = (lane < K) ? zi / Lc[lane * 65 + lane] : 0.0;
+    for (int k = K - 1; k >= 0; --k) {
+        const double yk = bcast64(w, k);
+        if (lane < k) w = __builtin_fma(-Lc[lane * 65 + k], yk, w);
     }
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const int i = lane + 64 * s;
-        if (i < K) y[i] = v[s];
-    }
+    if (lane < K) z[lane] = w;
+    __builtin_amdgcn_wave_barrier();
+    return true;
 }
 
 }  // namespace rorbk

@@ -59,6 +59,7 @@ struct Layout {
 struct rorbk_handle_s {
     rorbk::Layout L;
     hipStream_t stream;
+    int32_t ncu;              // compute units of the device
     double lambda;
     int32_t aligned;          // 16-byte vector loads allowed on the matrix
     int32_t aligned64;        // same for the FP64 master copy
@@ -124,6 +125,10 @@ struct rorbk_handle_s {
     int64_t rep_iters;
     // events
     hipEvent_t ev0, ev1;
+    hipEvent_t evr[2][2];     // residual timing (start, end) per poll slot
+    int32_t profile;
+    double prof_in_ms, prof_out_ms;
+    int64_t prof_in_n, prof_out_n;
 };
 
 namespace rorbk {
