@@ -108,12 +108,20 @@ def main():
     # timed: mixed (value), then FP64
     xm, im, tm = run(smix, True, K, profile=True)
     prof_m = smix.profile()
+    marks = [i for i in (1, 10, 100, 500, 1000, 2000, 3000, 4000, 5000, K) if i <= K]
+
+    def curve(sol):
+        h = sol.record()["rrn"]
+        return {str(i): float(h[i - 1]) for i in sorted(set(marks)) if i <= len(h)}
+
+    curve_m = curve(smix)
     log(f"mixed-{args.mixed}: {tm:.3f}s for {im['iters']} iters, rrn {im['rrn']:.3e}, "
         f"converged {im['converged']}, refine steps {im['n_refine']}")
     res = {}
     if not args.skip_extra:
         x64, i64, t64 = run(s64, False, K, profile=True)
         prof_64 = s64.profile()
+        res["rrn_curve"] = {"mixed": curve_m, "fp64": curve(s64)}
         log(f"fp64: {t64:.3f}s for {i64['iters']} iters, rrn {i64['rrn']:.3e}")
         res["fp64"] = {"time_s": t64, "iters": i64["iters"], "rrn": i64["rrn"],
                        "converged": i64["converged"],

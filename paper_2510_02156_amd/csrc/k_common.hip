@@ -121,47 +121,68 @@ constexpr int SEL_CHUNK = 4096;     // rows per selection chunk (upper bound)
 constexpr int SEL_MERGE = 8192;     // candidates per merge workgroup
 constexpr int SEL_BPC = 256;        // blocks per selection chunk (upper bound)
 
-// Exclusive scan of one 64-bit value per thread over the workgroup.
-__device__ __forceinline__ uint64_t block_exscan_u64(uint64_t v, uint64_t *sh, uint64_t *total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t inc = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
+// Largest and smallest of a per-thread 32-bit value over the workgroup: a
+// butterfly within each wave, then the per-wave results through LDS.  Every
+// thread receives both.  Contains one __syncthreads.
+__device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint32_t *omx,
+                                                 uint32_t *omn) {
+    __shared__ uint32_t wmx[16], wmn[16];
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)mx, off, 64);
+        const uint32_t c = (uint32_t)__shfl_xor((int)mn, off, 64);
+        mx = a > mx ? a : mx;
+        mn = c < mn ? c : mn;
     }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { wmx[w] = mx; wmn[w] = mn; }
     __syncthreads();
-    if (lane == 63) sh[w] = inc;
-    __syncthreads();
-    uint64_t base = 0, tot = 0;
-    const int nw = blockDim.x >> 6;
-    for (int i = 0; i < nw; ++i) {
-        if (i < w) base += sh[i];
-        tot += sh[i];
+    uint32_t a = wmx[0], c = wmn[0];
+    for (int i = 1; i < nw; ++i) {
+        a = wmx[i] > a ? wmx[i] : a;
+        c = wmn[i] < c ? wmn[i] : c;
     }
-    *total = tot;
-    __syncthreads();
-    return base + inc - v;
+    *omx = a;
+    *omn = c;
 }
 
-// Radix select over keys[0..N) in LDS, most significant byte first: finds a
-// masked threshold (T, mask) and the number `need` of elements whose masked key
-// equals T that complete the top K (elements with a larger masked key are all
-// in).  Stops as soon as the boundary digit's bucket holds exactly `need`
-// elements; otherwise continues to the last byte (then T is the exact K-th key).
-__device__ void radix_select(const uint64_t *keys, int N, int K, int nbits, uint64_t *T_out,
-                             uint64_t *mask_out, int *need_out) {
+// Radix select over keys[0..N) in LDS.  The 32-bit view (key >> shift) of the
+// largest and the smallest key (vmax, vmin, from block_minmax_u32) share
+// their leading bits with every key, so the search starts at the highest bit
+// where the two differ and spends no pass on a common prefix.  Digits of up to
+// 8 bits follow, most significant first: finds a masked threshold (T, mask)
+// and the number `need` of elements whose masked key equals T that complete
+// the top K (elements with a larger masked key are all in).  Stops as soon as
+// the boundary bucket holds exactly `need` elements.
+__device__ void radix_select(const uint64_t *keys, int N, int K, int shift, uint32_t vmax,
+                             uint32_t vmin, uint64_t *T_out, uint64_t *mask_out, int *need_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int s_need, s_stop;
-    if (threadIdx.x == 0) { s_prefix = 0; s_mask = 0; s_need = K; s_stop = 0; }
-    __syncthreads();
-    for (int shift = nbits - 8; shift >= 0; shift -= 8) {
+    const uint32_t dv = vmax ^ vmin;
+    if (dv == 0 && shift == 0) {  // all keys equal: the first K by index
+        *T_out = (uint64_t)vmax;
+        *mask_out = ~0ull;
+        *need_out = K;
+        return;
+    }
+    // highest differing bit (bit shift - 1 if the views agree)
+    const int top = dv ? shift + 31 - __clz((int)dv) : shift - 1;
+    if (threadIdx.x == 0) {
+        const uint64_t pm = ~((2ull << top) - 1ull);
+        s_prefix = ((uint64_t)vmax << shift) & pm;
+        s_mask = pm;
+        s_need = K;
+        s_stop = 0;
+    }
+    for (int hi = top; hi >= 0; hi -= 8) {
+        const int lo = hi >= 7 ? hi - 7 : 0;
+        const uint64_t dmask = (1ull << (hi - lo + 1)) - 1ull;
         for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix, mask = s_mask;
         for (int i = threadIdx.x; i < N; i += blockDim.x) {
             const uint64_t kk = keys[i];
-            if (((kk ^ prefix) & mask) == 0) atomicAdd(&hist[(kk >> shift) & 255], 1u);
+            if (((kk ^ prefix) & mask) == 0) atomicAdd(&hist[(kk >> lo) & dmask], 1u);
         }
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -178,8 +199,8 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int nbits, uint
             }
             const int need = s_need;
             const unsigned long long bal = __ballot(suf >= (uint32_t)need);
-            const int top = 63 - __clzll(bal);   // the highest lane reaching `need`
-            if (lane == top) {
+            const int topl = 63 - __clzll(bal);   // the highest lane reaching `need`
+            if (lane == topl) {
                 uint32_t above = suf - ls;
                 int bin = 4 * lane;
                 uint32_t inbin = h[0];
@@ -188,8 +209,8 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int nbits, uint
                     above += h[u];
                 }
                 s_need = need - (int)above;
-                s_prefix = prefix | ((uint64_t)bin << shift);
-                s_mask = mask | ((uint64_t)255 << shift);
+                s_prefix = prefix | ((uint64_t)bin << lo);
+                s_mask = mask | (dmask << lo);
                 s_stop = (inbin == (uint32_t)(need - (int)above)) ? 1 : 0;
             }
         }
@@ -204,37 +225,65 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int nbits, uint
 
 // Emit, in ascending index order, every element whose masked key exceeds T
 // and the first `need` elements whose masked key equals T (K in total).
-// keys/ids in LDS (ids == NULL: the position); outputs get base added.
+// Element i is taken by thread i % NT in round i / NT, so index order is
+// (round, wave, lane): ranks within a wave come from ballots, and the counts
+// of earlier (round, wave) pairs from one scan over their totals.  keys/ids
+// in LDS (ids == NULL: the position); outputs get base added.
+template <int NT, int ROUNDS>
 __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, int K, uint64_t T,
                              uint64_t mask, int need, uint64_t *okey, int32_t *oidx,
                              int32_t base) {
-    __shared__ uint64_t sh[16];
-    const int per = (N + blockDim.x - 1) / blockDim.x;
-    const int a = threadIdx.x * per, e = (a + per < N) ? a + per : N;
-    uint32_t gt = 0, eq = 0;
-    for (int i = a; i < e; ++i) {
-        const uint64_t mk = keys[i] & mask;
-        gt += mk > T;
-        eq += mk == T;
+    constexpr int NW = NT / 64, NS = ROUNDS * NW;
+    static_assert(NS <= 128, "one scan lane holds two (round, wave) totals");
+    // totals per (round, wave): greater-than count << 16 | equal count
+    // (each at most N <= 8192, so neither half carries into the other)
+    __shared__ uint32_t wcnt[NS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // per round: rank among the wave's "greater" lanes (bits 0..7), among its
+    // "equal" lanes (bits 8..15), and the two flags (bits 16, 17)
+    uint32_t rk[ROUNDS];
+#pragma unroll
+    for (int u = 0; u < ROUNDS; ++u) {
+        const int i = threadIdx.x + u * NT;
+        const uint64_t mk = (i < N) ? (keys[i] & mask) : 0;
+        const bool gt = (i < N) && mk > T, eq = (i < N) && mk == T;
+        const unsigned long long bg = __ballot(gt), be = __ballot(eq);
+        const uint32_t rg = __builtin_amdgcn_mbcnt_hi((uint32_t)(bg >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bg, 0u));
+        const uint32_t re = __builtin_amdgcn_mbcnt_hi((uint32_t)(be >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)be, 0u));
+        rk[u] = rg | (re << 8) | (gt ? 0x10000u : 0u) | (eq ? 0x20000u : 0u);
+        if (lane == 0) wcnt[u * NW + w] = ((uint32_t)__popcll(bg) << 16) | (uint32_t)__popcll(be);
     }
-    uint64_t tot;
-    const uint64_t ex = block_exscan_u64(((uint64_t)gt << 32) | eq, sh, &tot);
-    uint32_t g = (uint32_t)(ex >> 32), q = (uint32_t)(ex & 0xffffffffu);
-    for (int i = a; i < e; ++i) {
-        const uint64_t kk = keys[i], mk = kk & mask;
-        int pos = -1;
-        if (mk > T) {
-            pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
-            ++g;
-        } else if (mk == T) {
-            if (q < (uint32_t)need) pos = (int)(g + q);
-            ++q;
+    __syncthreads();
+    if (threadIdx.x < 64) {   // exclusive scan of the totals in (round, wave) order
+        const int a = 2 * lane;
+        const uint32_t c0 = (a < NS) ? wcnt[a] : 0u, c1 = (a + 1 < NS) ? wcnt[a + 1] : 0u;
+        uint32_t inc = c0 + c1;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += t;
         }
+        const uint32_t ex = inc - c0 - c1;
+        if (a < NS) wcnt[a] = ex;
+        if (a + 1 < NS) wcnt[a + 1] = ex + c0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < ROUNDS; ++u) {
+        const int i = threadIdx.x + u * NT;
+        const uint32_t before = wcnt[u * NW + w];
+        const uint32_t g = (before >> 16) + (rk[u] & 0xffu);
+        const uint32_t q = (before & 0xffffu) + ((rk[u] >> 8) & 0xffu);
+        int pos = -1;
+        if (rk[u] & 0x10000u) pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
+        else if ((rk[u] & 0x20000u) && q < (uint32_t)need) pos = (int)(g + q);
         if (pos >= 0 && pos < K) {
-            okey[pos] = kk;
+            okey[pos] = keys[i];
             oidx[pos] = (ids ? ids[i] : i) + base;
         }
     }
+    __syncthreads();
 }
 
 // Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
@@ -246,7 +295,6 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
     int64_t rem, int64_t k, int64_t bpc, int K, V *__restrict__ r, double *__restrict__ bn,
     double *__restrict__ cn, uint64_t *__restrict__ ckey, int32_t *__restrict__ cidx,
     int do_topk, const Ctrl *__restrict__ ctrl) {
-    if (ctrl && ctrl->done) return;
     __shared__ uint64_t keys[SEL_CHUNK];
     __shared__ double vals[SEL_CHUNK];
     __shared__ double s_bn[SEL_BPC];
@@ -255,7 +303,8 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
     const int64_t r0 = blk_start(t0, q, rem), r1 = blk_start(t1, q, rem);
     const int N = (int)(r1 - r0);
     constexpr int PER = SEL_CHUNK / SEL_T;
-    // every load of the chunk in flight at once
+    constexpr int SH = sizeof(V) == 8 ? 32 : 0;   // the 32-bit view of a key
+    // every load of the chunk in flight together with the stop flag's
     V bv[PER];
     double av[PER];
 #pragma unroll
@@ -276,26 +325,42 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
             for (int u = 0; u < PER; ++u) av[u] += t[u];
         }
     }
+    if (ctrl && ctrl->done) return;
+    uint32_t vmx = 0u, vmn = 0xffffffffu;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int i = threadIdx.x + u * SEL_T;
         if (i < N) {
             const V s = axp ? (V)((double)bv[u] - av[u]) : bv[u];
+            const uint64_t kk = key_of(s);
+            const uint32_t v = (uint32_t)(kk >> SH);
             r[r0 + i] = s;
             vals[i] = (double)s;
-            keys[i] = key_of(s);
+            keys[i] = kk;
+            vmx = v > vmx ? v : vmx;
+            vmn = v < vmn ? v : vmn;
         }
     }
-    __syncthreads();
-    // per-block squared norms: one wave per block, lanes stride the rows
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int64_t t = t0 + w; t < t1; t += nw) {
-        const int64_t s0 = blk_start(t, q, rem) - r0;
-        const int bt = blk_rows(t, q, rem);
-        double s = 0.0;
-        for (int i = lane; i < bt; i += 64) s = __builtin_fma(vals[s0 + i], vals[s0 + i], s);
-        s = group_sum(s, 64);
-        if (lane == 0) { bn[t] = s; s_bn[t - t0] = s; }
+    uint32_t vmax, vmin;
+    block_minmax_u32(vmx, vmn, &vmax, &vmin);   // also orders the LDS writes above
+    // per-block squared norms: 8 lanes per block, each summing every 8th row
+    // in order, then a fixed butterfly over the 8 lanes
+    {
+        const int nb = (int)(t1 - t0), j = threadIdx.x & 7;
+        for (int g = threadIdx.x >> 3; g < nb; g += SEL_T / 8) {
+            const int64_t t = t0 + g;
+            const int s0 = (int)(blk_start(t, q, rem) - r0);
+            const int bt = blk_rows(t, q, rem);
+            double s = 0.0;
+            for (int i = j; i < bt; i += 8) s = __builtin_fma(vals[s0 + i], vals[s0 + i], s);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 1, 64);
+            if (j == 0) {
+                bn[t] = s;
+                s_bn[g] = s;
+            }
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -306,9 +371,10 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
     if (!do_topk) return;
     uint64_t T, mask;
     int need;
-    radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &mask, &need);
-    compact_topk(keys, nullptr, N, K, T, mask, need, ckey + (int64_t)blockIdx.x * K,
-                 cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
+    radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
+    compact_topk<SEL_T, SEL_CHUNK / SEL_T>(keys, nullptr, N, K, T, mask, need,
+                                           ckey + (int64_t)blockIdx.x * K,
+                                           cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
 }
 
 // Merge groups of candidate lists (each K long, ascending rows) into K
@@ -336,6 +402,7 @@ __global__ __launch_bounds__(SEL_T) void k_select_merge(
     }
     if (do_topk) {
         constexpr int PER = SEL_MERGE / SEL_T;
+        constexpr int SH = sizeof(V) == 8 ? 32 : 0;
         uint64_t kv[PER];
         int32_t iv[PER];
 #pragma unroll
@@ -344,24 +411,32 @@ __global__ __launch_bounds__(SEL_T) void k_select_merge(
             kv[u] = (i < N) ? ckey[(int64_t)l0 * K + i] : 0;
             iv[u] = (i < N) ? cidx[(int64_t)l0 * K + i] : 0;
         }
+        uint32_t vmx = 0u, vmn = 0xffffffffu;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int i = threadIdx.x + u * SEL_T;
-            if (i < N) { keys[i] = kv[u]; ids[i] = iv[u]; }
+            if (i < N) {
+                keys[i] = kv[u];
+                ids[i] = iv[u];
+                const uint32_t v = (uint32_t)(kv[u] >> SH);
+                vmx = v > vmx ? v : vmx;
+                vmn = v < vmn ? v : vmn;
+            }
         }
-        __syncthreads();
+        uint32_t vmax, vmin;
+        block_minmax_u32(vmx, vmn, &vmax, &vmin);
         uint64_t T, mask;
         int need;
-        radix_select(keys, N, K, sizeof(V) == 8 ? 64 : 32, &T, &mask, &need);
+        radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
         if (!final_level) {
-            compact_topk(keys, ids, N, K, T, mask, need, okey + (int64_t)blockIdx.x * K,
-                         oidx + (int64_t)blockIdx.x * K, 0);
+            compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need,
+                                                   okey + (int64_t)blockIdx.x * K,
+                                                   oidx + (int64_t)blockIdx.x * K, 0);
             return;
         }
         __shared__ uint64_t fk[MAXB];
         __shared__ int32_t fi[MAXB];
-        compact_topk(keys, ids, N, K, T, mask, need, fk, fi, 0);
-        __syncthreads();
+        compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need, fk, fi, 0);
         for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
     }
     __syncthreads();
@@ -460,7 +535,7 @@ hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream
 // on one wave (K <= 64, MT = 0) or on MT x MT register tiles (larger K).  rhs = r_I (forward) or, for the
 // adjoint, -(sum of the partial products A_I g).
 template <int MT, int NTH>
-__global__ __launch_bounds__(NTH) void k_chol_solve(const double *__restrict__ Gpart, int nch,
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_solve(const double *__restrict__ Gpart, int nch,
                                                      int K, double lambda,
                                                      const double *__restrict__ rI,
                                                      const double *__restrict__ Pin, int nchP,

@@ -280,10 +280,19 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
     }
     if (upd)
         for (int c = tid; c < wcols; c += NT) x[c0 + c] = s_x[c];
+    // partial products of the next rows: lane sums staged in LDS, then each
+    // row's NV sums added in lane order by one thread
+    if (ncnt > 0) {
+        __shared__ V s_p[RPT * G * NV];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const V s = group_sum(pacc[r], NV);
-        if (v == 0 && nrow[r] >= 0) p.Pout[(int64_t)blockIdx.x * p.bmax + g + G * r] = (double)s;
+        for (int r = 0; r < RPT; ++r) s_p[(r * G + g) * NV + v] = pacc[r];
+        __syncthreads();
+        for (int row = tid; row < ncnt; row += NT) {
+            const V *pp = s_p + row * NV;   // row = g + G * r  ->  (r * G + g) = row
+            V s = (V)0;
+            for (int l = 0; l < NV; ++l) s += pp[l];
+            p.Pout[(int64_t)blockIdx.x * p.bmax + row] = (double)s;
+        }
     }
 }
 

@@ -365,49 +365,55 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 // sum_{i>k} l_ik y_i.  The steps are generated with compile-time k so that
 // every register index is static.
 template <int k>
-__device__ __forceinline__ bool ldl_step64(double (&a)[64], double &zi, int K, int lane,
-                                           double *colbuf, double *Lc) {
-    if (k >= K) return true;
+__device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, int lane, double *colbuf,
+                                           double *Lc, bool &ok) {
     const double *col = colbuf + (k & 1) * 64;
     double *nxt = colbuf + ((k + 1) & 1) * 64;
     const double d = bcast64(a[k], k);
-    if (!(d > 0.0)) return false;
+    ok = ok && (d > 0.0);
     const double inv = 1.0 / d;
     const double c = a[k] * inv;
     const double zk = bcast64(zi, k);
-    if (lane > k) zi = __builtin_fma(-c, zk, zi);
+    zi = (lane > k) ? __builtin_fma(-c, zk, zi) : zi;
     Lc[k * 65 + lane] = (lane > k) ? c : d;
+    // column k (rows > k) into registers first, then the row update
+    double cv[64];
+#pragma unroll
+    for (int j = k + 1; j < 64; ++j) cv[j] = col[j];
     if constexpr (k + 1 < 64) {
-        if (k + 1 < K) a[k + 1] = __builtin_fma(-c, col[k + 1], a[k + 1]);
+        a[k + 1] = __builtin_fma(-c, cv[k + 1], a[k + 1]);
         nxt[lane] = a[k + 1];
     }
 #pragma unroll
-    for (int j = k + 2; j < 64; ++j)
-        if (j < K) a[j] = __builtin_fma(-c, col[j], a[j]);
+    for (int j = k + 2; j < 64; ++j) a[j] = __builtin_fma(-c, cv[j], a[j]);
     __builtin_amdgcn_wave_barrier();
-    return true;
 }
 
 template <int... Ks>
-__device__ __forceinline__ bool ldl_steps64(std::integer_sequence<int, Ks...>, double (&a)[64],
-                                            double &zi, int K, int lane, double *colbuf,
-                                            double *Lc) {
-    return (ldl_step64<Ks>(a, zi, K, lane, colbuf, Lc) && ...);
+__device__ __forceinline__ void ldl_steps64(std::integer_sequence<int, Ks...>, double (&a)[64],
+                                            double &zi, int lane, double *colbuf, double *Lc,
+                                            bool &ok) {
+    (ldl_step64<Ks>(a, zi, lane, colbuf, Lc, ok), ...);
 }
 
+// The system is padded to 64 x 64 with the identity beyond K (zero right-hand
+// side), which leaves the leading K x K factor and solution unchanged and keeps
+// the 64 unrolled steps free of branches.
 __device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
                                   double *Lc /* 64*65 */) {
     const int lane = threadIdx.x & 63;
     double a[64];
 #pragma unroll
-    for (int j = 0; j < 64; ++j) a[j] = (j <= lane && lane < K) ? Gp[pk(lane, j)] : 0.0;
+    for (int j = 0; j < 64; ++j)
+        a[j] = (lane < K && j < K) ? ((j <= lane) ? Gp[pk(lane, j)] : 0.0) : (j == lane ? 1.0 : 0.0);
     double zi = (lane < K) ? z[lane] : 0.0;
     colbuf[lane] = a[0];
     __builtin_amdgcn_wave_barrier();
-    if (!ldl_steps64(std::make_integer_sequence<int, 64>{}, a, zi, K, lane, colbuf, Lc))
-        return false;
+    bool ok = true;
+    ldl_steps64(std::make_integer_sequence<int, 64>{}, a, zi, lane, colbuf, Lc, ok);
+    if (!ok) return false;
     // backward substitution, column oriented
-    double w = (lane < K) ? zi / Lc[lane * 65 + lane] : 0.0;
+    double w = zi / Lc[lane * 65 + lane];
     for (int k = K - 1; k >= 0; --k) {
         const double yk = bcast64(w, k);
         if (lane < k) w = __builtin_fma(-Lc[lane * 65 + k], yk, w);
