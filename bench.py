@@ -38,6 +38,44 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str, mixed: str):
+    """HBM bytes per launch of the residual kernel from the committed
+    byte-counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy),
+    used only if the counters were taken from the kernel source as it is now;
+    otherwise None."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_resid_dense_{mixed}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    hs = re.search(r"kernel_source_sha256: ([0-9a-f]{64})", text)
+    tb = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not hs or not tb:
+        return None
+    h = hashlib.sha256()
+    for f in ("k_resid.hip", "rorbk_device.h"):
+        with open(os.path.join(ROOT, "paper_2510_02156_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(tb.group(1)) if h.hexdigest() == hs.group(1) else None
+
+
+def copy_calibration(mib: int):
+    """A plain streaming copy (dst = -src) of known size: under a byte-counter
+    profile, the counters it reads give the scale between counted and moved
+    bytes on this part."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        torch.neg(src, out=dst)   # one streaming elementwise kernel: reads and writes nbytes
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,7 +90,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-extra", action="store_true",
                     help="time only the mixed solve (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the "
+                         "reference kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
@@ -130,6 +174,9 @@ def main():
                        if prof_64["inner_ms"] > 0 else None}
         res["speedup_mixed_vs_fp64"] = t64 / tm
         xs = w["xstar"]
+        # the returned iterates measured by one FP64 residual pass each
+        res["rrn_of_returned_x"] = {"mixed": float(s64.residual(b, xm)[2]),
+                                    "fp64": float(s64.residual(b, x64)[2])}
         res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
                                    "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
 
@@ -139,7 +186,8 @@ def main():
     ms = prof_m["inner_ms"]
     achieved = bytes_resid / (ms * 1e-3) / 1e9 if ms > 0 else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": (achieved / PEAK_HBM_GBS) if achieved else None, "traffic": None,
+            "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+            "traffic": measured_traffic(args.workload, args.mixed),
             "kernel": f"k_resid_dense<{args.mixed}>", "bytes_per_launch": bytes_resid,
             "avg_launch_ms": ms, "launches_timed": prof_m["inner_n"]}
 
