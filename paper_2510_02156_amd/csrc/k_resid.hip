@@ -9,12 +9,16 @@ constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 
 // ------------------------------------------------------------ residual pass --
 // Algorithm 1, r = b - A x: the products (A x)_i over one 2048-column segment.
-// A persistent grid (a few workgroups per CU) walks the rows: wave w takes rows
-// w*ROWS, w*ROWS + nwaves*ROWS, ..., ROWS rows in flight at a time.  Each lane
-// keeps its 32 entries of x in registers and streams the row with 16-byte
-// non-temporal loads; lane sums are combined by a fixed butterfly.
-// axp[seg][i] = partial (A x)_i; the selection kernel subtracts the segment sum
-// from b.  Grid: x = workgroups, y = segments.
+// A persistent grid (two workgroups per CU) walks the rows: wave w takes rows
+// w*ROWS .. w*ROWS+ROWS-1, then the same rows plus nwaves*ROWS, and so on.
+// For each group of ROWS rows every 16-byte load of the group is issued
+// (non-temporal, raw bytes) before any of them is converted or used, so each
+// wave keeps ROWS * SEG * sizeof(T) bytes in flight; then each row's lane
+// sums (FMA in column order) are combined by a fixed butterfly.  Each lane
+// keeps its entries of x in registers.  Rows past the end re-read the last
+// row (in bounds) and discard the result.  axp[seg][i] = partial (A x)_i; the
+// selection kernel subtracts the segment sum from b.  Grid: x = workgroups,
+// y = segments.
 template <typename T, typename V, bool AL, int ROWS>
 __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
@@ -36,26 +40,29 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
     }
     const int64_t nwaves = (int64_t)gridDim.x * 4;
     const int64_t stride = nwaves * ROWS;
+    const uvec4 zero = {0u, 0u, 0u, 0u};
     for (int64_t i = ((int64_t)blockIdx.x * 4 + w) * ROWS; i < m; i += stride) {
-        V acc[ROWS];
+        uvec4 raw[ROWS][NVL];
 #pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) acc[rr] = (V)0;
+        for (int rr = 0; rr < ROWS; ++rr) {
+            const int64_t row = (i + rr < m) ? i + rr : m - 1;
 #pragma unroll
-        for (int s = 0; s < NVL; ++s) {
-            const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
-#pragma unroll
-            for (int rr = 0; rr < ROWS; ++rr) {
-                if (i + rr < m && col < n) {
-                    V a[VW];
-                    load_vec_nt<T, V, AL>(A + (i + rr) * ld, col, n, a);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) acc[rr] = fmaT(a[e], xr[s][e], acc[rr]);
-                }
+            for (int s = 0; s < NVL; ++s) {
+                const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
+                raw[rr][s] = (col < n) ? load_raw_nt<T, AL>(A + row * ld, col, n) : zero;
             }
         }
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
-            const V sres = group_sum(acc[rr], WAVE);
+            V acc = (V)0;
+#pragma unroll
+            for (int s = 0; s < NVL; ++s) {
+                V a[VW];
+                cvt_raw<T, V>(raw[rr][s], a);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc = fmaT(a[e], xr[s][e], acc);
+            }
+            const V sres = group_sum(acc, WAVE);
             if (lane == 0 && i + rr < m) axp[seg * m + i + rr] = (double)sres;
         }
     }
@@ -65,9 +72,9 @@ template <typename T, typename V, int ROWS>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
                               const void *x, double *axp, hipStream_t s) {
     const Layout &L = h->L;
-    // persistent grid: 4 workgroups (16 waves) per CU, fewer for short matrices
+    // persistent grid: 2 workgroups (8 waves) per CU, fewer for short matrices
     int64_t groups = (L.m + 4 * ROWS - 1) / (4 * ROWS);
-    const int64_t cap = 4 * (int64_t)h->ncu;
+    const int64_t cap = 2 * (int64_t)h->ncu;
     if (groups > cap) groups = cap;
     dim3 grid((unsigned)groups, (unsigned)L.nseg);
     if (aligned)
@@ -84,6 +91,8 @@ hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt,
                                  int vec, const void *x, double *axp, hipStream_t s) {
     if (vec == VEC_F64) {
         if (dt != RORBK_F64) return hipErrorInvalidValue;
+        // the unaligned FP64 form needs twice the registers per row in flight
+        if (aligned) return resid_typed<double, double, 2>(h, A, aligned, x, axp, s);
         return resid_typed<double, double, 1>(h, A, aligned, x, axp, s);
     }
     if (dt == RORBK_F32) return resid_typed<float, float, 2>(h, A, aligned, x, axp, s);

@@ -140,6 +140,16 @@ __device__ __forceinline__ uvec4 load_raw(const T *__restrict__ row, int64_t c, 
     return w;
 }
 
+// As load_raw, with the full 16-byte load marked non-temporal (streamed
+// once, not kept in the caches).
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ uvec4 load_raw_nt(const T *__restrict__ row, int64_t c, int64_t lim) {
+    constexpr int VW = Tr<T>::VW;
+    if (ALIGNED && c + VW <= lim)
+        return __builtin_nontemporal_load(reinterpret_cast<const uvec4 *>(row + c));
+    return load_raw<T, ALIGNED>(row, c, lim);
+}
+
 template <typename T, typename V>
 __device__ __forceinline__ void cvt_raw(const uvec4 &w, V (&out)[Tr<T>::VW]) {
     if constexpr (sizeof(T) == 8) {
