@@ -647,17 +647,21 @@ hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A, i
     else RORBK_BG(bf16_t);
 #undef RORBK_BG
     e = hipGetLastError();
-    if (e == hipSuccess) {
-        if (L.bmax <= 64)
-            hipLaunchKernelGGL(k_block_inverse64, dim3((unsigned)L.k), dim3(64), 0, s, Gs, kp,
-                               L.q, L.rem, h->lambda, h->d_H, d_fail);
-        else
-            hipLaunchKernelGGL(k_block_inverse<8>, dim3((unsigned)L.k), dim3(256), 0, s, Gs, kp,
-                               L.q, L.rem, h->lambda, h->d_H, d_fail);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = launch_block_inverses_from_grams(h, Gs, kp, d_fail, s);
     hipError_t e2 = hipFreeAsync(Gs, s);
     return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_block_inverses_from_grams(const rorbk_handle_s *h, const double *Gs, int64_t kp,
+                                            int32_t *d_fail, hipStream_t s) {
+    const Layout &L = h->L;
+    if (L.bmax <= 64)
+        hipLaunchKernelGGL(k_block_inverse64, dim3((unsigned)L.k), dim3(64), 0, s, Gs, kp, L.q,
+                           L.rem, h->lambda, h->d_H, d_fail);
+    else
+        hipLaunchKernelGGL(k_block_inverse<8>, dim3((unsigned)L.k), dim3(256), 0, s, Gs, kp, L.q,
+                           L.rem, h->lambda, h->d_H, d_fail);
+    return hipGetLastError();
 }
 
 }  // namespace rorbk

@@ -117,10 +117,6 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_W);
     dfree(h->d_hoff);
     dfree(h->d_H);
-    dfree(h->d_tptr);
-    dfree(h->d_tcol);
-    dfree(h->d_tseg);
-    dfree(h->d_trow);
     dfree(h->d_ctrl);
     if (h->h_ctrl) (void)hipHostFree(h->h_ctrl);
     h->h_ctrl = nullptr;
@@ -155,17 +151,20 @@ void destroy_all(rorbk_handle_s *h) {
 // ----------------------------------------------------------- dispatch ----
 
 hipError_t step(const rorbk_handle_s *h, const StepArgs &a) {
+    if (h->L.format == RORBK_CSR) return launch_step_csr(h, a, h->stream);
     return launch_step_dense(h, a, h->stream);
 }
 
 hipError_t residual(const rorbk_handle_s *h, const void *A, int dt, int aligned, int vec,
                     const void *x, double *axp) {
+    if (h->L.format == RORBK_CSR) return launch_residual_csr(h, A, dt, vec, x, axp, h->stream);
     return launch_residual_dense(h, A, dt, aligned, vec, x, axp, h->stream);
 }
 
 hipError_t gram(const rorbk_handle_s *h, const void *A, int dt, int aligned, const int32_t *idx,
                 int K, double *G) {
     (void)aligned;
+    if (h->L.format == RORBK_CSR) return launch_gram_csr(h, A, dt, idx, K, G, h->stream);
     return launch_gram_dense(h, A, dt, idx, K, G, h->stream);
 }
 
@@ -404,15 +403,17 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
                                           (long long)A->m, (long long)A->n);
     if (A->m > INT32_MAX || A->n > INT32_MAX)
         return fail(RORBK_ERR_UNSUPPORTED, "dimensions above 2^31 are not supported");
-    if (!A->values) return fail(RORBK_ERR_INVALID_ARG, "matrix values pointer is NULL");
+    if (!A->values && !(A->format == RORBK_CSR && A->nnz == 0))
+        return fail(RORBK_ERR_INVALID_ARG, "matrix values pointer is NULL");
     if (A->format == RORBK_DENSE && A->ld < A->n)
         return fail(RORBK_ERR_INVALID_ARG, "ld %lld < n %lld", (long long)A->ld, (long long)A->n);
     if (A->format == RORBK_CSR) {
-        if (!A->rowptr || !A->colidx || A->nnz < 0)
-            return fail(RORBK_ERR_INVALID_ARG, "CSR needs rowptr, colidx and nnz >= 0");
+        if (!A->rowptr || A->nnz < 0)
+            return fail(RORBK_ERR_INVALID_ARG, "CSR needs rowptr and nnz >= 0");
         if (A->dtype == RORBK_BF16)
             return fail(RORBK_ERR_UNSUPPORTED, "BF16 storage is dense only");
-        return fail(RORBK_ERR_UNSUPPORTED, "CSR path not built in this library");
+        if (A->nnz > 0 && (!A->colidx || !A->values))
+            return fail(RORBK_ERR_INVALID_ARG, "CSR with nnz > 0 needs colidx and values");
     }
     if (block_rows < 1 || block_rows > A->m)
         return fail(RORBK_ERR_INVALID_ARG, "block_rows %lld outside [1, m=%lld]",
@@ -447,8 +448,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     h->A64 = (A->dtype == RORBK_F64) ? (const double *)A->values : A->values_f64;
     h->rowptr = A->rowptr;
     h->colidx = A->colidx;
-    h->aligned = aligned16(A->values, L.ld, dtype_size(A->dtype)) ? 1 : 0;
-    h->aligned64 = (h->A64 && aligned16(h->A64, L.ld, 8)) ? 1 : 0;
+    const bool dense = A->format == RORBK_DENSE;
+    h->aligned = (dense && aligned16(A->values, L.ld, dtype_size(A->dtype))) ? 1 : 0;
+    h->aligned64 = (dense && h->A64 && aligned16(h->A64, L.ld, 8)) ? 1 : 0;
     h->refine_inner = 50;
     h->refine_eta = 1e-4;
     {
@@ -522,6 +524,24 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return code;
     };
     hipStream_t s = h->stream;
+    if (L.format == RORBK_CSR) {
+        int32_t *d_bad = nullptr;
+        rc = dalloc(&d_bad, 1);
+        if (rc) return bail(rc);
+        int32_t zero = 0, hbad = 0;
+        hipError_t e1 = hipMemcpyAsync(d_bad, &zero, 4, hipMemcpyHostToDevice, s);
+        hipError_t e2 = launch_csr_check(h, d_bad, s);
+        hipError_t e3 = hipMemcpyAsync(&hbad, d_bad, 4, hipMemcpyDeviceToHost, s);
+        hipError_t e4 = hipStreamSynchronize(s);
+        dfree(d_bad);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess)
+            return bail(fail(RORBK_ERR_HIP, "CSR check failed: %s",
+                             hipGetErrorString(e2 != hipSuccess ? e2 : e4)));
+        if (hbad)
+            return bail(fail(RORBK_ERR_INVALID_ARG,
+                             "CSR arrays invalid (rowptr not monotone from 0 to nnz, or column "
+                             "indices not strictly ascending in [0, n) within a row)"));
+    }
     if (launch_partition(L.m, k, h->d_off, h->d_hoff, s) != hipSuccess)
         return bail(fail(RORBK_ERR_HIP, "partition launch failed"));
     // centroid cosines and the proposal
@@ -531,7 +551,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         double *scratch = nullptr;
         rc = dalloc(&scratch, (size_t)len);
         if (rc) return bail(rc);
-        hipError_t le = launch_setup_proposal_dense(h, h->A, L.dtype, h->aligned, scratch, s);
+        hipError_t le = (L.format == RORBK_CSR)
+                            ? launch_setup_proposal_csr(h, h->A, L.dtype, scratch, s)
+                            : launch_setup_proposal_dense(h, h->A, L.dtype, h->aligned, scratch, s);
         hipError_t se = hipStreamSynchronize(s);
         dfree(scratch);
         if (le != hipSuccess || se != hipSuccess)
@@ -545,7 +567,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         if (rc) return bail(rc);
         int32_t zero = 0, hfail = 0;
         hipError_t e1 = hipMemcpyAsync(d_fail, &zero, 4, hipMemcpyHostToDevice, s);
-        hipError_t e2 = launch_block_inverses_dense(h, h->A, L.dtype, h->aligned, d_fail, s);
+        hipError_t e2 = (L.format == RORBK_CSR)
+                            ? launch_block_inverses_csr(h, h->A, L.dtype, d_fail, s)
+                            : launch_block_inverses_dense(h, h->A, L.dtype, h->aligned, d_fail, s);
         hipError_t e3 = hipMemcpyAsync(&hfail, d_fail, 4, hipMemcpyDeviceToHost, s);
         hipError_t e4 = hipStreamSynchronize(s);
         dfree(d_fail);

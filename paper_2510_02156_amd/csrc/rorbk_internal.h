@@ -73,13 +73,6 @@ struct rorbk_handle_s {
     double *d_S, *d_pbar, *d_W;
     int64_t *d_hoff;          // k+1 offsets into d_H
     double *d_H;              // stored block inverses
-    // CSR: transposed layout of each fixed block for A_t^T y
-    int64_t *d_tptr;          // per block: offset of its column list (k+1)
-    int32_t *d_tcol;          // unique columns of each block, ascending
-    int64_t *d_tseg;          // per unique column: start in d_trow/d_tval (+1 sentinel per block)
-    int32_t *d_trow;          // local row index of each entry
-    int64_t tcols_total;
-
     // per-solve workspaces (owned)
     rorbk::Ctrl *d_ctrl;
     rorbk::Ctrl *h_ctrl;      // pinned mirror
@@ -156,14 +149,17 @@ hipError_t launch_setup_proposal_dense(const rorbk_handle_s *h, const void *A,
 hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A,
                                        int dt, int aligned, int32_t *d_fail,
                                        hipStream_t s);
-// CSR setup
-hipError_t launch_setup_proposal_csr(rorbk_handle_s *h, const void *vals, int dt,
-                                     double *scratch, int64_t scratch_len,
-                                     hipStream_t s);
-hipError_t launch_block_inverses_csr(const rorbk_handle_s *h, const void *vals,
-                                     int dt, int32_t *d_fail, hipStream_t s);
-hipError_t launch_csr_transpose_blocks(rorbk_handle_s *h, hipStream_t s);
-
+hipError_t launch_proposal_from_centroids(const rorbk_handle_s *h, double *cen, double *nrm,
+                                          double *Sp, hipStream_t s);
+// stored inverses (G_t + lambda I)^{-1} from packed block Grams Gs[t][kp]
+hipError_t launch_block_inverses_from_grams(const rorbk_handle_s *h, const double *Gs,
+                                            int64_t kp, int32_t *d_fail, hipStream_t s);
+// CSR setup (values of dtype dt with the handle's rowptr / colidx)
+hipError_t launch_csr_check(const rorbk_handle_s *h, int32_t *bad, hipStream_t s);
+hipError_t launch_setup_proposal_csr(const rorbk_handle_s *h, const void *vals, int dt,
+                                     double *scratch, hipStream_t s);
+hipError_t launch_block_inverses_csr(const rorbk_handle_s *h, const void *vals, int dt,
+                                     int32_t *d_fail, hipStream_t s);
 // iteration kernels (dense or CSR chosen from the handle's format)
 struct StepArgs {
     const void *A;        // matrix values (dtype dt)
@@ -180,11 +176,6 @@ struct StepArgs {
     RowSel nxt;           // rows whose partial products are produced
     double *Pout;
 };
-hipError_t launch_step(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
-
-hipError_t launch_residual(const rorbk_handle_s *h, const void *A, int dt,
-                           int aligned, int vec, const void *x, double *axp,
-                           hipStream_t s);
 
 // selection: builds r = b - sum(axp), block norms, candidates; then the final
 // merge writes I, r_I, the RRN record and the stop flag.
@@ -207,9 +198,6 @@ struct SelectArgs {
 };
 hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream_t s);
 
-hipError_t launch_gram(const rorbk_handle_s *h, const void *A, int dt, int aligned,
-                       const int32_t *idx, int K, double *Gpart, hipStream_t s);
-
 // rhs: rI (forward) or -(sum of partials) (adjoint)
 hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                              const double *rI, const double *Pin, double *y,
@@ -227,12 +215,17 @@ hipError_t launch_init_ctrl(Ctrl *c, double tol, const double *bnorm2, hipStream
 hipError_t launch_set_thr(Ctrl *c, double thr, hipStream_t s);
 hipError_t launch_axpy_f64(const double *d, double *x, int64_t n, hipStream_t s);
 
-// format-specific pieces behind launch_step / launch_residual / launch_gram
+// format-specific block step, residual products and greedy Gram
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
 hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt,
                                  int aligned, int vec, const void *x, double *axp,
                                  hipStream_t s);
 hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt,
                              const int32_t *idx, int K, double *Gpart, hipStream_t s);
+hipError_t launch_step_csr(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
+hipError_t launch_residual_csr(const rorbk_handle_s *h, const void *vals, int dt, int vec,
+                               const void *x, double *axp, hipStream_t s);
+hipError_t launch_gram_csr(const rorbk_handle_s *h, const void *vals, int dt,
+                           const int32_t *idx, int K, double *Gpart, hipStream_t s);
 
 }  // namespace rorbk
