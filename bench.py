@@ -7,6 +7,9 @@ workload's cap is 5000).  A step is one outer ROR-BK iteration: three sampled
 block updates, the full residual pass with per-block norms and the stop test,
 the top-K greedy selection and the greedy block update.
 
+Other workloads (``--workload``): ``csr_200000`` (sparse square CSR, FP32
+values for the inner passes), ``wide_2000x50000``, ``dense_2000x200``.
+
 Timed: the mixed-precision solve (FP32 storage for the inner passes, FP64
 outer residual and refinement; `value`) and the all-FP64 solve on the same
 matrix, inputs resident in HBM.  The residual-pass kernel is timed with HIP
@@ -105,36 +108,67 @@ def main():
 
     import torch
     import paper_2510_02156_amd as P
-    from workloads import make, to_bf16_bits
+    from workloads import WORKLOADS, make, to_bf16_bits
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     t0 = time.time()
     w = make(args.workload)
     log(f"generated {args.workload} in {time.time() - t0:.1f}s")
-    A64h, bh = w["A"], w["b"]
-    m, n = A64h.shape
+    bh = w["b"]
     br, lam, tol, seed = w["block_rows"], w["lam"], w["tol"], w["seed"]
-    A64 = torch.from_numpy(A64h).to(dev)
     b = torch.from_numpy(bh).to(dev)
-    A32 = A64.float()
-    Abf = torch.from_numpy(to_bf16_bits(A64h).view(np.int16)).view(torch.bfloat16).to(dev)
-    torch.cuda.synchronize()
-
-    t0 = time.time()
-    s64 = P.Solver(A64, br, lam)
-    torch.cuda.synchronize()
-    t_setup64 = time.time() - t0
-    Amix = A32 if args.mixed == "f32" else Abf
-    t0 = time.time()
-    smix = P.Solver(Amix, br, lam, A64=A64)
-    torch.cuda.synchronize()
-    t_setupmix = time.time() - t0
+    csr = w["format"] == "csr"
+    if csr:
+        if args.mixed != "f32":
+            raise SystemExit("sparse storage is FP64 or FP32 only")
+        m, n = w["m"], w["n"]
+        nnz = len(w["val"])
+        rowptr = torch.from_numpy(w["rowptr"]).to(dev)
+        colidx = torch.from_numpy(w["colidx"]).to(dev)
+        V64 = torch.from_numpy(w["val"]).to(dev)
+        V32 = V64.float()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s64 = P.Solver(None, br, lam, rowptr=rowptr, colidx=colidx, values=V64, shape=(m, n))
+        torch.cuda.synchronize()
+        t_setup64 = time.time() - t0
+        t0 = time.time()
+        smix = P.Solver(None, br, lam, rowptr=rowptr, colidx=colidx, values=V32, shape=(m, n),
+                        A64=V64)
+        torch.cuda.synchronize()
+        t_setupmix = time.time() - t0
+        oracle_A = w
+    else:
+        A64h = w["A"]
+        m, n = A64h.shape
+        nnz = m * n
+        A64 = torch.from_numpy(A64h).to(dev)
+        A32 = A64.float()
+        Abf = torch.from_numpy(to_bf16_bits(A64h).view(np.int16)).view(torch.bfloat16).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s64 = P.Solver(A64, br, lam)
+        torch.cuda.synchronize()
+        t_setup64 = time.time() - t0
+        Amix = A32 if args.mixed == "f32" else Abf
+        t0 = time.time()
+        smix = P.Solver(Amix, br, lam, A64=A64)
+        torch.cuda.synchronize()
+        t_setupmix = time.time() - t0
+        oracle_A = A64h
     smix.set_refine(args.inner, 1e-4)
     log(f"setup: fp64 {t_setup64:.3f}s, mixed-{args.mixed} {t_setupmix:.3f}s "
         f"(k={s64.k}, K={s64.K})")
 
     K = args.steps
+
+    def resid_bytes(es, xs):
+        """Algorithmic bytes of one residual pass: the matrix once (values, and
+        for CSR the column indices and row offsets), x once, the products written."""
+        if csr:
+            return nnz * (es + 4) + (m + 1) * 8 + n * xs + m * 8
+        return m * n * es + n * xs + m * 8
 
     def run(sol, refine, iters, profile=False):
         x = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -170,7 +204,7 @@ def main():
         res["fp64"] = {"time_s": t64, "iters": i64["iters"], "rrn": i64["rrn"],
                        "converged": i64["converged"],
                        "resid_kernel_ms": prof_64["inner_ms"],
-                       "resid_GBs": (m * n * 8 + n * 8 + m * 8) / (prof_64["inner_ms"] * 1e-3) / 1e9
+                       "resid_GBs": resid_bytes(8, 8) / (prof_64["inner_ms"] * 1e-3) / 1e9
                        if prof_64["inner_ms"] > 0 else None}
         res["speedup_mixed_vs_fp64"] = t64 / tm
         xs = w["xstar"]
@@ -182,28 +216,34 @@ def main():
 
     # roofline of the dominant kernel: the inner residual pass of the mixed solve
     es = 4 if args.mixed == "f32" else 2
-    bytes_resid = m * n * es + n * 4 + m * 8       # A once, x, the partial (A x) write
+    bytes_resid = resid_bytes(es, 4)
     ms = prof_m["inner_ms"]
     achieved = bytes_resid / (ms * 1e-3) / 1e9 if ms > 0 else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-            "traffic": measured_traffic(args.workload, args.mixed),
-            "kernel": f"k_resid_dense<{args.mixed}>", "bytes_per_launch": bytes_resid,
+            "traffic": None if csr else measured_traffic(args.workload, args.mixed),
+            "kernel": (f"k_csr_spmv<{args.mixed}>" if csr else f"k_resid_dense<{args.mixed}>"),
+            "bytes_per_launch": bytes_resid,
             "avg_launch_ms": ms, "launches_timed": prof_m["inner_n"]}
 
     # CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
-        probe = O.solve(w, br, lam, bh, seed=seed, tol=tol, max_iters=3, record=False)
+        t0 = time.time()
+        Wo = O.proposal(O.cosine_rowsums(oracle_A, br), n)[1]     # the oracle's own proposal
+        t_prop = time.time() - t0
+        probe = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=3, W=Wo,
+                        record=False)
         per = max(probe["t_iter_s"] / 3, 1e-4)
         N = int(min(2000, max(10, args.cpu_seconds / per)))
         log(f"oracle: setup {probe['t_setup_s']:.2f}s, {per * 1e3:.1f} ms/iter; sample {N} iters")
-        ref = O.solve(w, br, lam, bh, seed=seed, tol=tol, max_iters=N, record=False)
+        ref = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N, W=Wo, record=False)
         per = ref["t_iter_s"] / max(ref["iters"], 1)
         cpu = {"value": per * K, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": (f"FP64 oracle setup once ({ref['t_setup_s']:.2f}s, not counted) + "
-                          f"{ref['iters']} outer iterations on the full {m}x{n} matrix; "
+               "sample": (f"FP64 oracle setup once (proposal {t_prop:.2f}s + block factors "
+                          f"{ref['t_setup_s']:.2f}s, not counted) + "
+                          f"{ref['iters']} outer iterations on the full {m}x{n} system; "
                           f"per-iteration time x {K} steps"),
                "iters_per_s": 1.0 / per}
         # GPU solves against the oracle over the same N iterations
@@ -229,8 +269,9 @@ def main():
         "vs_baseline": None,
         "dtype": f"{args.mixed}+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "m": m, "n": n, "block_rows": br,
-                   "lambda": lam, "cond": 1e8, "tol": tol, "cap_iters": K,
+        "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "block_rows": br,
+                   "lambda": lam, "cond": WORKLOADS[args.workload].get("cond"), "tol": tol,
+                   "cap_iters": K,
                    "mixed": f"{args.mixed} storage inner passes, FP64 refinement every "
                             f"{args.inner} inner iterations",
                    "parallelism": "single GPU"},

@@ -198,6 +198,7 @@ def test_csr_invalid_input_rejected():
                  shape=(s["m"], s["n"]))
 
 
+@pytest.mark.timeout(600)
 def test_csr_full_size():
     """The full sparse workload (200000^2, 2.6M entries, blocks of 128): the
     setup's S for every block, sampled block inverses, and three free-running

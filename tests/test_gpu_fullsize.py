@@ -1,0 +1,110 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times: the tall dense 100000 x 2000 system (FP64 and FP32 storage),
+the wide 2000 x 50000 system, and the 2000 x 200 system over the whole
+5000-iteration cap.  Outputs the oracle computes one by one (S of every
+block, sampled block inverses, a few iterations) are compared directly; the
+wide case also checks Lemma 2's range-space property, which holds at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import make
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2510_02156_amd as P  # noqa: E402
+from tests.gpu_util import dev, host, rel  # noqa: E402
+
+
+def check_setup(sol, A, br, lam, blocks):
+    got = sol.setup_arrays()
+    np.testing.assert_array_equal(got["offsets"], O.partition(A.shape[0], br))
+    S = O.cosine_rowsums(A, br)
+    np.testing.assert_allclose(got["S"], S, rtol=1e-12)
+    off = got["offsets"]
+    for t in blocks:
+        rows = np.arange(off[t], off[t + 1])
+        L = O.block_factor(A, rows, lam)
+        G = L @ L.T
+        assert rel(sol.block_inverse(t), np.linalg.inv(G)) < 50 * np.linalg.cond(G) * 2.2e-16
+
+
+@pytest.mark.timeout(600)
+def test_tall_full_size():
+    w = make("tall_100000x2000")
+    A, br, lam, seed = w["A"], w["block_rows"], w["lam"], w["seed"]
+    print("tall full size: FP64 setup", flush=True)
+    A64 = dev(A)
+    sol = P.Solver(A64, br, lam)
+    check_setup(sol, A, br, lam, (0, 31, 32, 1000, sol.k - 1))
+    iters = 5
+    ref = O.solve(A, br, lam, w["b"], seed=seed, max_iters=iters)
+    x, info = sol.solve(dev(w["b"]), seed=seed, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"tall full size FP64: {iters} iterations rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+    # FP32 storage, oracle on the same rounded values with its selections replayed
+    A32h = A.astype(np.float32)
+    Av = A32h.astype(np.float64)
+    b32 = Av @ w["xstar"]
+    ref32 = O.solve(Av, br, lam, b32, seed=seed, max_iters=iters)
+    s32 = P.Solver(A64.float(), br, lam)
+    s32.set_replay(ref32["tau"], ref32["I"], iters)
+    x32, _ = s32.solve(dev(b32, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
+    e32 = rel(host(x32), ref32["x"])
+    print(f"tall full size FP32: {iters} iterations rel err {e32:.2e}", flush=True)
+    assert e32 < 1e-4
+
+
+@pytest.mark.timeout(300)
+def test_wide_full_size():
+    w = make("wide_2000x50000")
+    A, br, lam, seed = w["A"], w["block_rows"], w["lam"], w["seed"]
+    print("wide full size: setup", flush=True)
+    sol = P.Solver(dev(A), br, lam)
+    check_setup(sol, A, br, lam, (0, 15, 16, sol.k - 1))
+    iters = 20
+    ref = O.solve(A, br, lam, w["b"], seed=seed, max_iters=iters)
+    x, _ = sol.solve(dev(w["b"]), seed=seed, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    xh = host(x)
+    e = rel(xh, ref["x"])
+    # Lemma 2: from x0 = 0 every iterate stays in the row space of A
+    coef = np.linalg.solve(A @ A.T, A @ xh)
+    null_part = xh - A.T @ coef
+    ratio = np.linalg.norm(null_part) / np.linalg.norm(xh)
+    print(f"wide full size: rel err {e:.2e}, null-space share {ratio:.2e}", flush=True)
+    assert e < 1e-10
+    assert ratio < 1e-9
+
+
+@pytest.mark.timeout(300)
+def test_dense_2000x200_whole_cap():
+    """All 5000 iterations of the 2000 x 200 workload, replaying the oracle's
+    selections: the error stays bounded because every step is non-expansive."""
+    w = make("dense_2000x200")
+    A, br, lam, seed = w["A"], w["block_rows"], w["lam"], w["seed"]
+    iters = w["max_iters"]
+    ref = O.solve(A, br, lam, w["b"], seed=seed, tol=w["tol"], max_iters=iters)
+    sol = P.Solver(dev(A), br, lam)
+    sol.set_replay(ref["tau"], ref["I"], ref["iters"])
+    x, info = sol.solve(dev(w["b"]), seed=0, tol=w["tol"], max_iters=ref["iters"], replay=True)
+    rec = sol.record()
+    e = rel(host(x), ref["x"])
+    print(f"2000x200 over {ref['iters']} iterations: rel err {e:.2e}; RRN oracle "
+          f"{ref['rrn']:.3e} GPU {info['rrn']:.3e}", flush=True)
+    assert info["iters"] == ref["iters"] and info["converged"] == ref["converged"]
+    assert e < 1e-10
+    np.testing.assert_allclose(rec["rrn"], ref["rrn_hist"], rtol=1e-8)
+    # free running reaches the same draws (generated up front from W)
+    x2, _ = sol.solve(dev(w["b"]), seed=seed, tol=w["tol"], max_iters=50, record=True)
+    np.testing.assert_array_equal(sol.record()["tau"], ref["tau"][:150])
