@@ -213,6 +213,26 @@ def main():
                                     "fp64": float(s64.residual(b, x64)[2])}
         res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
                                    "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
+        if not csr:
+            # the other 16-/32-bit storage beside the one timed as `value`
+            other = "bf16" if args.mixed == "f32" else "f32"
+            Aoth = Abf if other == "bf16" else A32
+            soth = P.Solver(Aoth, br, lam, A64=A64)
+            soth.set_refine(args.inner, 1e-4)
+            run(soth, True, args.warmup)
+            xo, io, to = run(soth, True, K, profile=True)
+            po = soth.profile()
+            eo = 2 if other == "bf16" else 4
+            log(f"mixed-{other}: {to:.3f}s for {io['iters']} iters")
+            res[f"mixed_{other}"] = {
+                "time_s": to, "iters": io["iters"], "converged": io["converged"],
+                "speedup_vs_fp64": t64 / to,
+                "rrn_of_returned_x": float(s64.residual(b, xo)[2]),
+                "rrn_curve": curve(soth),
+                "resid_kernel_ms": po["inner_ms"],
+                "resid_GBs": resid_bytes(eo, 4) / (po["inner_ms"] * 1e-3) / 1e9
+                if po["inner_ms"] > 0 else None}
+            soth.close()
 
     # roofline of the dominant kernel: the inner residual pass of the mixed solve
     es = 4 if args.mixed == "f32" else 2

@@ -286,18 +286,159 @@ __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, in
     __syncthreads();
 }
 
+// Merge of nlists candidate lists (each K long, ascending rows) from ckey /
+// cidx into the K largest, in LDS keys / ids (N = nlists * K <= SEL_MERGE).
+template <typename V>
+__device__ void merge_lists(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
+                            int N, int K, uint64_t *keys, int32_t *ids, uint64_t *okey,
+                            int32_t *oidx) {
+    constexpr int PER = SEL_MERGE / SEL_T;
+    constexpr int SH = sizeof(V) == 8 ? 32 : 0;
+    uint64_t kv[PER];
+    int32_t iv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * SEL_T;
+        kv[u] = (i < N) ? ckey[i] : 0;
+        iv[u] = (i < N) ? cidx[i] : 0;
+    }
+    uint32_t vmx = 0u, vmn = 0xffffffffu;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * SEL_T;
+        if (i < N) {
+            keys[i] = kv[u];
+            ids[i] = iv[u];
+            const uint32_t v = (uint32_t)(kv[u] >> SH);
+            vmx = v > vmx ? v : vmx;
+            vmn = v < vmn ? v : vmn;
+        }
+    }
+    uint32_t vmax, vmin;
+    block_minmax_u32(vmx, vmn, &vmax, &vmin);
+    uint64_t T, mask;
+    int need;
+    radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
+    compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need, okey, oidx, 0);
+}
+
+// The end of an iteration's selection (one workgroup): the last candidate
+// merge (if do_topk), the RRN from the chunk norms in chunk order, the stop
+// test, the greedy set I (or the replayed one) with r_I, and the records.
+// keys / ids / s_cn: LDS of SEL_MERGE, SEL_MERGE and SEL_MERGE / 4 entries.
+template <typename V>
+__device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
+                             int nlists, int K, const double *__restrict__ cn, int ncn,
+                             const V *__restrict__ r, Ctrl *__restrict__ ctrl, int stop_test,
+                             int do_topk, int64_t it, double *rec_rrn, int32_t *rec_I,
+                             const int32_t *replay_I, int32_t *I_out, double *rI_out,
+                             uint64_t *keys, int32_t *ids, double *s_cn) {
+    __shared__ int s_stop;
+    __shared__ uint64_t fk[MAXB];
+    __shared__ int32_t fi[MAXB];
+    constexpr int NCN = SEL_MERGE / 4;
+    for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
+    if (do_topk) {
+        merge_lists<V>(ckey, cidx, nlists * K, K, keys, ids, fk, fi);
+        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double rn2 = 0.0;
+        for (int c = 0; c < ncn; ++c) rn2 += (c < NCN) ? s_cn[c] : cn[c];
+        const double rn = sqrt(rn2);
+        ctrl->rnorm2 = rn2;
+        ctrl->last_it = it;
+        const double bn2 = ctrl->bnorm2;
+        const double rrn = (bn2 > 0.0) ? rn / sqrt(bn2) : 0.0;
+        if (rec_rrn) rec_rrn[it] = rrn;
+        int stop = 0;
+        if (!isfinite(rn2)) {
+            ctrl->status = RORBK_ERR_NONFINITE;
+            stop = 1;
+        } else if (stop_test && rn < ctrl->thr) {
+            stop = 1;
+        }
+        if (stop) {
+            ctrl->done = 1;
+            ctrl->conv_it = it;
+        }
+        s_stop = stop;
+    }
+    __syncthreads();
+    if (s_stop || !I_out) return;
+    for (int p = threadIdx.x; p < K; p += blockDim.x) {
+        const int32_t row = replay_I ? replay_I[it * K + p] : ids[p];
+        I_out[p] = row;
+        rI_out[p] = (double)r[row];
+        if (rec_I) rec_I[it * K + p] = row;
+    }
+}
+
+// Candidate merge levels for long residuals: groups of lists_per_group lists
+// (each K long) into K candidates per group; the last level (one group) ends
+// the iteration's selection.
+template <typename V>
+__global__ __launch_bounds__(SEL_T) void k_select_merge(
+    const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx, int nlists,
+    int lists_per_group, int K, uint64_t *__restrict__ okey, int32_t *__restrict__ oidx,
+    int final_level, const double *__restrict__ cn, int ncn, const V *__restrict__ r,
+    Ctrl *__restrict__ ctrl, int stop_test, int do_topk, int64_t it, double *rec_rrn,
+    int32_t *rec_I, const int32_t *replay_I, int32_t *I_out, double *rI_out) {
+    if (ctrl->done) return;
+    __shared__ uint64_t keys[SEL_MERGE];
+    __shared__ int32_t ids[SEL_MERGE];
+    __shared__ double s_cn[SEL_MERGE / 4];
+    if (final_level) {
+        select_final<V>(ckey, cidx, nlists, K, cn, ncn, r, ctrl, stop_test, do_topk, it, rec_rrn,
+                        rec_I, replay_I, I_out, rI_out, keys, ids, s_cn);
+        return;
+    }
+    const int l0 = blockIdx.x * lists_per_group;
+    const int l1 = (l0 + lists_per_group < nlists) ? l0 + lists_per_group : nlists;
+    merge_lists<V>(ckey + (int64_t)l0 * K, cidx + (int64_t)l0 * K, (l1 - l0) * K, K, keys, ids,
+                   okey + (int64_t)blockIdx.x * K, oidx + (int64_t)blockIdx.x * K);
+}
+
+// What the last chunk workgroup needs to end the selection itself (fused
+// form): see select_final.
+template <typename V>
+struct SelFinal {
+    uint32_t *counter;     // NULL: not fused (a merge kernel follows)
+    int nlists;
+    const double *cn;
+    int ncn;
+    Ctrl *ctrl;
+    int stop_test;
+    int64_t it;
+    double *rec_rrn;
+    int32_t *rec_I;
+    const int32_t *replay_I;
+    int32_t *I_out;
+    double *rI_out;
+};
+
+// LDS of the selection kernels: a chunk's keys, values and block norms, then
+// (fused form, last workgroup) the merge's keys, indices and chunk norms.
+constexpr int SEL_LDS = (SEL_MERGE * 8 + SEL_MERGE * 4 + (SEL_MERGE / 4) * 8) / 8;
+
 // Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
 // (Algorithm 1, the full residual), per-block ||r_t||^2, the chunk's ||r||^2,
-// and the chunk's local top-K candidates (keys, global row indices).
+// and the chunk's local top-K candidates (keys, global row indices).  Fused
+// form (fin.counter set): every workgroup publishes its results (release
+// fence), counts itself done, and the last one (acquire fence) merges the
+// candidates and ends the selection, so no second kernel is launched.
 template <typename V>
 __global__ __launch_bounds__(SEL_T) void k_select_chunk(
     const V *__restrict__ b, const double *__restrict__ axp, int nseg, int64_t m, int64_t q,
     int64_t rem, int64_t k, int64_t bpc, int K, V *__restrict__ r, double *__restrict__ bn,
     double *__restrict__ cn, uint64_t *__restrict__ ckey, int32_t *__restrict__ cidx,
-    int do_topk, const Ctrl *__restrict__ ctrl) {
-    __shared__ uint64_t keys[SEL_CHUNK];
-    __shared__ double vals[SEL_CHUNK];
-    __shared__ double s_bn[SEL_BPC];
+    int do_topk, const Ctrl *__restrict__ ctrl, SelFinal<V> fin) {
+    __shared__ uint64_t sel_lds[SEL_LDS];
+    __shared__ int s_last;
+    uint64_t *keys = sel_lds;                                   // SEL_CHUNK
+    double *vals = reinterpret_cast<double *>(sel_lds + SEL_CHUNK);   // SEL_CHUNK
+    double *s_bn = reinterpret_cast<double *>(sel_lds + 2 * SEL_CHUNK); // SEL_BPC
     const int64_t t0 = (int64_t)blockIdx.x * bpc;
     const int64_t t1 = (t0 + bpc < k) ? t0 + bpc : k;
     const int64_t r0 = blk_start(t0, q, rem), r1 = blk_start(t1, q, rem);
@@ -368,133 +509,74 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
         for (int64_t t = t0; t < t1; ++t) s += s_bn[t - t0];
         cn[blockIdx.x] = s;
     }
-    if (!do_topk) return;
-    uint64_t T, mask;
-    int need;
-    radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
-    compact_topk<SEL_T, SEL_CHUNK / SEL_T>(keys, nullptr, N, K, T, mask, need,
-                                           ckey + (int64_t)blockIdx.x * K,
-                                           cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
-}
-
-// Merge groups of candidate lists (each K long, ascending rows) into K
-// candidates per group.  The last level (one group) finishes the iteration:
-// RRN from the chunk norms in chunk order, the stop test, the greedy set I
-// (or the replayed one) with r_I, and the records.
-template <typename V>
-__global__ __launch_bounds__(SEL_T) void k_select_merge(
-    const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx, int nlists,
-    int lists_per_group, int K, uint64_t *__restrict__ okey, int32_t *__restrict__ oidx,
-    int final_level, const double *__restrict__ cn, int ncn, const V *__restrict__ r,
-    Ctrl *__restrict__ ctrl, int stop_test, int do_topk, int64_t it, double *rec_rrn,
-    int32_t *rec_I, const int32_t *replay_I, int32_t *I_out, double *rI_out) {
-    if (ctrl->done) return;
-    __shared__ uint64_t keys[SEL_MERGE];
-    __shared__ int32_t ids[SEL_MERGE];
-    __shared__ double s_cn[SEL_MERGE / 4];
-    __shared__ int s_stop;
-    const int l0 = blockIdx.x * lists_per_group;
-    const int l1 = (l0 + lists_per_group < nlists) ? l0 + lists_per_group : nlists;
-    const int N = (l1 - l0) * K;
-    constexpr int NCN = SEL_MERGE / 4;
-    if (final_level) {
-        for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
-    }
     if (do_topk) {
-        constexpr int PER = SEL_MERGE / SEL_T;
-        constexpr int SH = sizeof(V) == 8 ? 32 : 0;
-        uint64_t kv[PER];
-        int32_t iv[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + u * SEL_T;
-            kv[u] = (i < N) ? ckey[(int64_t)l0 * K + i] : 0;
-            iv[u] = (i < N) ? cidx[(int64_t)l0 * K + i] : 0;
-        }
-        uint32_t vmx = 0u, vmn = 0xffffffffu;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int i = threadIdx.x + u * SEL_T;
-            if (i < N) {
-                keys[i] = kv[u];
-                ids[i] = iv[u];
-                const uint32_t v = (uint32_t)(kv[u] >> SH);
-                vmx = v > vmx ? v : vmx;
-                vmn = v < vmn ? v : vmn;
-            }
-        }
-        uint32_t vmax, vmin;
-        block_minmax_u32(vmx, vmn, &vmax, &vmin);
         uint64_t T, mask;
         int need;
         radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
-        if (!final_level) {
-            compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need,
-                                                   okey + (int64_t)blockIdx.x * K,
-                                                   oidx + (int64_t)blockIdx.x * K, 0);
-            return;
-        }
-        __shared__ uint64_t fk[MAXB];
-        __shared__ int32_t fi[MAXB];
-        compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need, fk, fi, 0);
-        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
+        compact_topk<SEL_T, SEL_CHUNK / SEL_T>(keys, nullptr, N, K, T, mask, need,
+                                               ckey + (int64_t)blockIdx.x * K,
+                                               cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
     }
+    if (!fin.counter) return;
+    // count this workgroup done; the acquire-release device-scope atomic
+    // publishes its r, norms and candidates and, for the last one, makes
+    // every other workgroup's visible
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double rn2 = 0.0;
-        for (int c = 0; c < ncn; ++c) rn2 += (c < NCN) ? s_cn[c] : cn[c];
-        const double rn = sqrt(rn2);
-        ctrl->rnorm2 = rn2;
-        ctrl->last_it = it;
-        const double bn2 = ctrl->bnorm2;
-        const double rrn = (bn2 > 0.0) ? rn / sqrt(bn2) : 0.0;
-        if (rec_rrn) rec_rrn[it] = rrn;
-        int stop = 0;
-        if (!isfinite(rn2)) {
-            ctrl->status = RORBK_ERR_NONFINITE;
-            stop = 1;
-        } else if (stop_test && rn < ctrl->thr) {
-            stop = 1;
-        }
-        if (stop) {
-            ctrl->done = 1;
-            ctrl->conv_it = it;
-        }
-        s_stop = stop;
-    }
+    if (threadIdx.x == 0)
+        s_last = (__hip_atomic_fetch_add(fin.counter, 1u, __ATOMIC_ACQ_REL,
+                                         __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) ? 1 : 0;
     __syncthreads();
-    if (s_stop || !I_out) return;
-    for (int p = threadIdx.x; p < K; p += blockDim.x) {
-        const int32_t row = replay_I ? replay_I[it * K + p] : ids[p];
-        I_out[p] = row;
-        rI_out[p] = (double)r[row];
-        if (rec_I) rec_I[it * K + p] = row;
-    }
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) *fin.counter = 0u;   // ready for the next launch
+    select_final<V>(ckey, cidx, fin.nlists, K, fin.cn, fin.ncn, r, fin.ctrl, fin.stop_test,
+                    do_topk, fin.it, fin.rec_rrn, fin.rec_I, fin.replay_I, fin.I_out, fin.rI_out,
+                    sel_lds, reinterpret_cast<int32_t *>(sel_lds + SEL_MERGE),
+                    reinterpret_cast<double *>(sel_lds + SEL_MERGE + SEL_MERGE / 2));
 }
+
 
 hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream_t s) {
     const Layout &L = h->L;
     const int K = (int)L.K;
     const int do_topk = (!a.skip_topk && !a.replay_I) ? 1 : 0;
-    if (a.vec == VEC_F64)
-        hipLaunchKernelGGL(k_select_chunk<double>, dim3(L.nch_s), dim3(SEL_T), 0, s,
-                           (const double *)a.b, a.axp, a.nseg, L.m, L.q, L.rem, L.k, L.bpc, K,
-                           (double *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
-                           h->d_ctrl);
-    else
-        hipLaunchKernelGGL(k_select_chunk<float>, dim3(L.nch_s), dim3(SEL_T), 0, s,
-                           (const float *)a.b, a.axp, a.nseg, L.m, L.q, L.rem, L.k, L.bpc, K,
-                           (float *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,
-                           h->d_ctrl);
+    // one merge of all chunk candidates fits a workgroup: fuse it into the
+    // chunk kernel (its last workgroup); otherwise merge in levels
+    const int per = SEL_MERGE / K;
+    const bool fuse = !do_topk || L.nch_s <= per;
+#define RORBK_SEL(V)                                                                            \
+    do {                                                                                        \
+        SelFinal<V> fin = {};                                                                   \
+        if (fuse) {                                                                             \
+            fin.counter = h->d_selcnt;                                                          \
+            fin.nlists = L.nch_s;                                                               \
+            fin.cn = h->d_cn;                                                                   \
+            fin.ncn = L.nch_s;                                                                  \
+            fin.ctrl = h->d_ctrl;                                                               \
+            fin.stop_test = a.stop_test;                                                        \
+            fin.it = a.it;                                                                      \
+            fin.rec_rrn = a.record_rrn ? a.rec_rrn : nullptr;                                   \
+            fin.rec_I = a.record_I ? a.rec_I : nullptr;                                         \
+            fin.replay_I = a.replay_I;                                                          \
+            fin.I_out = a.I_out;                                                                \
+            fin.rI_out = a.rI_out;                                                              \
+        }                                                                                       \
+        hipLaunchKernelGGL(k_select_chunk<V>, dim3(L.nch_s), dim3(SEL_T), 0, s,                 \
+                           (const V *)a.b, a.axp, a.nseg, L.m, L.q, L.rem, L.k, L.bpc, K,       \
+                           (V *)a.r, h->d_bn, h->d_cn, h->d_ckey, h->d_cidx, do_topk,           \
+                           h->d_ctrl, fin);                                                     \
+    } while (0)
+    if (a.vec == VEC_F64) RORBK_SEL(double);
+    else RORBK_SEL(float);
+#undef RORBK_SEL
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || fuse) return e;
     // merge levels: lists of K candidates, at most SEL_MERGE per workgroup
     int nlists = L.nch_s;
-    const int per = SEL_MERGE / K;
     const uint64_t *ik = h->d_ckey;
     const int32_t *ii = h->d_cidx;
     int flip = 0;
-    while (do_topk && nlists > per) {
+    while (nlists > per) {
         const int groups = (nlists + per - 1) / per;
         uint64_t *ok = flip ? h->d_ckey : h->d_ckey2;
         int32_t *oi = flip ? h->d_cidx : h->d_cidx2;

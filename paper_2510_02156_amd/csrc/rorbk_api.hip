@@ -135,6 +135,7 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_y);
     dfree(h->d_G);
     dfree(h->d_red);
+    dfree(h->d_selcnt);
     dfree(h->d_rhs32);
     dfree(h->d_d32);
     dfree(h->d_r64);
@@ -502,6 +503,7 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_y, bmax);
     ALLOC(h->d_G, (int64_t)L.nch_g * K * (K + 1) / 2);
     ALLOC(h->d_red, 64);
+    ALLOC(h->d_selcnt, 1);
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_ctrl, 3 * sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -510,6 +512,11 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return fail(RORBK_ERR_OOM, "pinned allocation failed: %s", hipGetErrorString(e));
     }
     memset(h->h_ctrl, 0, 3 * sizeof(Ctrl));
+    if (hipMemsetAsync(h->d_selcnt, 0, sizeof(uint32_t), (hipStream_t)stream) != hipSuccess) {
+        destroy_all(h);
+        delete h;
+        return fail(RORBK_ERR_HIP, "clearing the selection counter failed");
+    }
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
         hipEventCreate(&h->evr[0][0]) != hipSuccess || hipEventCreate(&h->evr[0][1]) != hipSuccess ||
         hipEventCreate(&h->evr[1][0]) != hipSuccess || hipEventCreate(&h->evr[1][1]) != hipSuccess) {

@@ -76,6 +76,7 @@ struct rorbk_handle_s {
     // per-solve workspaces (owned)
     rorbk::Ctrl *d_ctrl;
     rorbk::Ctrl *h_ctrl;      // pinned mirror
+    uint32_t *d_selcnt;       // selection workgroups done (fused merge), 0 between launches
     double *d_P[2];           // partial A_S x per update chunk [nch][bmax]
     double *d_axp;            // residual partial products [nseg][m]
     void *d_r;                // residual (vector type)
