@@ -225,16 +225,23 @@ __global__ __launch_bounds__(256) void k_csr_centroid(const int64_t *__restrict_
 //      with the stored inverse of block t; (ymode 1) y given; (ymode 2) no
 //      update;
 //   2. x += A_S^T y: the block's entries are taken in row order, in chunks of
-//      CSR_CHUNK; within a chunk each entry's term a_ij y_i goes to a hash slot
-//      of its column; a column with one term gets x_j + term, a column with
-//      several gets x_j + (their sum in row order), so every x_j is written
-//      once per chunk by one thread;
-//   3. Pout[i] = A_{S'} x for the next step's rows S'.
+//      CSR_CHUNK; within a chunk each entry's column goes to a hash slot; a
+//      column with one term a_ij y_i gets x_j + term, a column with several
+//      gets x_j + (their sum in row order), so every x_j is written once per
+//      chunk by one thread;
+//   3. Pout[i] = A_{S'} x for the next step's rows S' (entry products summed in
+//      entry order per row).
+// Everything that does not depend on y or on the new x is fetched first: the
+// row offsets, the first chunk's entries and their hash slots, and the next
+// rows' entries (when they fit CSR_NCAP), so the dependent part is the stored
+// inverse product, one read-modify-write of x and one gather of x.
 // With b == NULL the step is the adjoint one: gb[S] -= y.
 constexpr int CSR_STEP_T = 512;
 constexpr int CSR_CHUNK = 2048;         // entries per update chunk
 constexpr int CSR_HASH = 4096;          // hash slots (a power of two >= 2 * CSR_CHUNK)
 constexpr int CSR_HASH_BITS = 12;
+constexpr int CSR_NCAP = 2048;          // next-row entries prefetched (4 per thread)
+constexpr int CSR_TPR = 4;              // threads per row of the stored-inverse product
 
 struct CsrStepP {
     const int64_t *rowptr;
@@ -255,10 +262,96 @@ struct CsrStepP {
     const Ctrl *ctrl;
 };
 
+// Entries [base, base + ne) of the row set (offsets off, starts p0) into the
+// chunk arrays: column, value, local row, and a hash slot per distinct column
+// (h_cnt: entries per slot, h_head: the first entry of the slot).
 template <typename T, typename V>
-__global__ __launch_bounds__(CSR_STEP_T) void k_csr_step(CsrStepP p) {
+__device__ __forceinline__ void csr_stage_chunk(const int32_t *__restrict__ colidx,
+                                                const T *__restrict__ val, const int64_t *off,
+                                                const int64_t *p0, int cnt, int64_t base, int ne,
+                                                int32_t *e_col, V *e_val, int16_t *e_row,
+                                                int32_t *e_slot, int32_t *h_key, int32_t *h_head,
+                                                uint32_t *h_cnt) {
+    for (int e = threadIdx.x; e < ne; e += CSR_STEP_T) {
+        const int64_t ge = base + e;
+        const int r = row_of_entry(off, cnt, ge);
+        const int64_t pp = p0[r] + (ge - off[r]);
+        const int32_t c = colidx[pp];
+        e_col[e] = c;
+        e_val[e] = (V)val[pp];
+        e_row[e] = (int16_t)r;
+        uint32_t sl = ((uint32_t)c * 2654435761u) >> (32 - CSR_HASH_BITS);
+        while (true) {
+            const int32_t old = atomicCAS(&h_key[sl], -1, c);
+            if (old == -1 || old == c) break;
+            sl = (sl + 1) & (CSR_HASH - 1);
+        }
+        e_slot[e] = (int32_t)sl;
+        atomicAdd(&h_cnt[sl], 1u);
+        atomicMin(&h_head[sl], e);
+    }
+}
+
+__device__ __forceinline__ void csr_clear_hash(int32_t *h_key, int32_t *h_head, uint32_t *h_cnt) {
+    for (int s = threadIdx.x; s < CSR_HASH; s += CSR_STEP_T) {
+        h_key[s] = -1;
+        h_head[s] = 0x7fffffff;
+        h_cnt[s] = 0u;
+    }
+}
+
+// x += the staged chunk's terms e_val[e] * y[e_row[e]]: one write per column.
+template <typename V>
+__device__ __forceinline__ void csr_apply_chunk(V *__restrict__ x, int ne, const double *s_y,
+                                                const int32_t *e_col, V *e_val,
+                                                const int16_t *e_row, const int32_t *e_slot,
+                                                const int32_t *h_head, const uint32_t *h_cnt,
+                                                int32_t *s_dup, int *s_ndup) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int NW = CSR_STEP_T / WAVE;
+    for (int e = tid; e < ne; e += CSR_STEP_T) e_val[e] = e_val[e] * (V)s_y[e_row[e]];
+    __syncthreads();
+    for (int e = tid; e < ne; e += CSR_STEP_T) {
+        const int sl = e_slot[e];
+        if (h_head[sl] == e) {
+            if (h_cnt[sl] == 1u) {
+                const int32_t c = e_col[e];
+                x[c] = x[c] + e_val[e];
+            } else {
+                s_dup[atomicAdd(s_ndup, 1)] = e;
+            }
+        }
+    }
+    __syncthreads();
+    // columns with several terms: one wave each, terms in entry order
+    const int nd = *s_ndup;
+    for (int d = wv; d < nd; d += NW) {
+        const int e0 = s_dup[d];
+        const int sl = e_slot[e0];
+        V acc = (V)0;
+        for (int b0 = e0; b0 < ne; b0 += WAVE) {
+            const int e = b0 + lane;
+            const bool hit = e < ne && e_slot[e] == sl;
+            unsigned long long bits = __ballot(hit);
+            if (lane == 0) {
+                while (bits) {
+                    const int bit = __ffsll((long long)bits) - 1;
+                    acc = acc + e_val[b0 + bit];
+                    bits &= bits - 1;
+                }
+            }
+        }
+        if (lane == 0) {
+            const int32_t c = e_col[e0];
+            x[c] = x[c] + acc;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(CSR_STEP_T) void k_csr_step(CsrStepP p) {
+    const int tid = threadIdx.x;
     const T *__restrict__ val = (const T *)p.val;
     V *__restrict__ x = (V *)p.x;
     const V *__restrict__ b = (const V *)p.b;
@@ -283,12 +376,16 @@ __global__ __launch_bounds__(CSR_STEP_T) void k_csr_step(CsrStepP p) {
 
     __shared__ double s_r[MAXB], s_y[MAXB];
     __shared__ int64_t s_len[MAXB], s_off[MAXB + 1], s_p0[MAXB];
+    __shared__ int64_t n_len[MAXB], n_off[MAXB + 1], n_p0[MAXB];
     __shared__ int32_t e_col[CSR_CHUNK], e_slot[CSR_CHUNK], s_dup[CSR_CHUNK];
+    __shared__ int16_t e_row[CSR_CHUNK];
     __shared__ V e_val[CSR_CHUNK];
+    __shared__ V n_prod[CSR_NCAP];
     __shared__ int32_t h_key[CSR_HASH], h_head[CSR_HASH];
     __shared__ uint32_t h_cnt[CSR_HASH];
     __shared__ int s_ndup;
 
+    // A. row offsets of both row sets; b - Pin or the given y
     if (upd) {
         for (int i = tid; i < cnt; i += CSR_STEP_T) {
             const int64_t row = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : cst + i;
@@ -298,104 +395,141 @@ __global__ __launch_bounds__(CSR_STEP_T) void k_csr_step(CsrStepP p) {
             if (p.ymode == 0) s_r[i] = (b ? (double)b[row] : 0.0) - p.Pin[i];
             else s_y[i] = p.ygiven[i];
         }
-        __syncthreads();
-        if (p.ymode == 0) {
-            const double *__restrict__ H = p.H + blk_hoff(tc, p.q, p.rem);
-            for (int i = tid; i < cnt; i += CSR_STEP_T) {
-                double s = 0.0;
-                for (int j = 0; j < cnt; ++j) s = __builtin_fma(H[(int64_t)j * cnt + i], s_r[j], s);
-                s_y[i] = s;
+    }
+    for (int i = tid; i < ncnt; i += CSR_STEP_T) {
+        const int64_t row = (p.nxt.kind == 1) ? (int64_t)p.nxt.idx[i] : nst + i;
+        const int64_t p0 = p.rowptr[row];
+        n_p0[i] = p0;
+        n_len[i] = p.rowptr[row + 1] - p0;
+    }
+    if (upd) csr_clear_hash(h_key, h_head, h_cnt);
+    if (tid == 0) s_ndup = 0;
+    __syncthreads();
+    if (upd) wave0_exscan(s_len, cnt, s_off);
+    if (ncnt > 0 && tid >= WAVE && tid < 2 * WAVE) {
+        // the same scan on wave 1 for the next rows
+        const int lane = tid - WAVE;
+        int64_t carry = 0;
+        for (int c0 = 0; c0 < ncnt; c0 += WAVE) {
+            const int64_t v = (c0 + lane < ncnt) ? n_len[c0 + lane] : 0;
+            int64_t inc = v;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int64_t t = __shfl_up(inc, o, WAVE);
+                if (lane >= o) inc += t;
             }
+            if (c0 + lane < ncnt) n_off[c0 + lane] = carry + inc - v;
+            carry += __shfl(inc, WAVE - 1, WAVE);
         }
-        wave0_exscan(s_len, cnt, s_off);
-        __syncthreads();
-        if (p.gb) {
-            V *gb = (V *)p.gb;
-            for (int i = tid; i < cnt; i += CSR_STEP_T) {
-                const int64_t row = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : cst + i;
-                gb[row] -= (V)s_y[i];
-            }
-        }
-        const int64_t tot = s_off[cnt];
-        for (int64_t base = 0; base < tot; base += CSR_CHUNK) {
-            const int ne = (int)((tot - base < CSR_CHUNK) ? tot - base : CSR_CHUNK);
-            for (int s = tid; s < CSR_HASH; s += CSR_STEP_T) {
-                h_key[s] = -1;
-                h_head[s] = 0x7fffffff;
-                h_cnt[s] = 0u;
-            }
-            if (tid == 0) s_ndup = 0;
-            __syncthreads();
-            for (int e = tid; e < ne; e += CSR_STEP_T) {
-                const int64_t ge = base + e;
-                const int r = row_of_entry(s_off, cnt, ge);
-                const int64_t pp = s_p0[r] + (ge - s_off[r]);
-                const int32_t c = p.colidx[pp];
-                e_col[e] = c;
-                e_val[e] = (V)val[pp] * (V)s_y[r];
-                uint32_t sl = ((uint32_t)c * 2654435761u) >> (32 - CSR_HASH_BITS);
-                while (true) {
-                    const int32_t old = atomicCAS(&h_key[sl], -1, c);
-                    if (old == -1 || old == c) break;
-                    sl = (sl + 1) & (CSR_HASH - 1);
-                }
-                e_slot[e] = (int32_t)sl;
-                atomicAdd(&h_cnt[sl], 1u);
-                atomicMin(&h_head[sl], e);
-            }
-            __syncthreads();
-            for (int e = tid; e < ne; e += CSR_STEP_T) {
-                const int sl = e_slot[e];
-                if (h_head[sl] == e) {
-                    if (h_cnt[sl] == 1u) {
-                        const int32_t c = e_col[e];
-                        x[c] = x[c] + e_val[e];
-                    } else {
-                        s_dup[atomicAdd(&s_ndup, 1)] = e;
-                    }
-                }
-            }
-            __syncthreads();
-            // columns with several terms: one wave each, terms in entry order
-            const int nd = s_ndup;
-            for (int d = wv; d < nd; d += NW) {
-                const int e0 = s_dup[d];
-                const int sl = e_slot[e0];
-                V acc = (V)0;
-                for (int b0 = e0; b0 < ne; b0 += WAVE) {
-                    const int e = b0 + lane;
-                    const bool hit = e < ne && e_slot[e] == sl;
-                    unsigned long long bits = __ballot(hit);
-                    if (lane == 0) {
-                        while (bits) {
-                            const int bit = __ffsll((long long)bits) - 1;
-                            acc = acc + e_val[b0 + bit];
-                            bits &= bits - 1;
-                        }
-                    }
-                }
-                if (lane == 0) {
-                    const int32_t c = e_col[e0];
-                    x[c] = x[c] + acc;
-                }
-            }
-            __syncthreads();
+        if (lane == 0) n_off[ncnt] = carry;
+    }
+    __syncthreads();
+    const int64_t tot = upd ? s_off[cnt] : 0;
+    const int64_t ntot = (ncnt > 0) ? n_off[ncnt] : 0;
+    // B. the next rows' entries (x-independent) into registers
+    const bool npre = ntot <= CSR_NCAP;
+    constexpr int NU = CSR_NCAP / CSR_STEP_T;
+    int32_t ncol[NU];
+    T nval[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int e = tid + u * CSR_STEP_T;
+        ncol[u] = 0;
+        nval[u] = (T)0;
+        if (npre && e < ntot) {
+            const int r = row_of_entry(n_off, ncnt, e);
+            const int64_t pp = n_p0[r] + (e - n_off[r]);
+            ncol[u] = p.colidx[pp];
+            nval[u] = val[pp];
         }
     }
-    // products of the next rows with the updated x
-    if (ncnt > 0) {
-        const int sub = tid % SPMV_LPR;
-        for (int i0 = 0; i0 < ncnt; i0 += CSR_STEP_T / SPMV_LPR) {
-            const int i = i0 + tid / SPMV_LPR;
-            V acc = (V)0;
-            if (i < ncnt) {
-                const int64_t row = (p.nxt.kind == 1) ? (int64_t)p.nxt.idx[i] : nst + i;
-                const int64_t p1 = p.rowptr[row + 1];
-                for (int64_t pp = p.rowptr[row] + sub; pp < p1; pp += SPMV_LPR)
-                    acc = fmaT((V)val[pp], x[p.colidx[pp]], acc);
+    // C. the first chunk of this block's entries with their hash slots
+    const int ne0 = (int)((tot < CSR_CHUNK) ? tot : CSR_CHUNK);
+    if (upd)
+        csr_stage_chunk<T, V>(p.colidx, val, s_off, s_p0, cnt, 0, ne0, e_col, e_val, e_row,
+                              e_slot, h_key, h_head, h_cnt);
+    // D. y = H_t r_S: CSR_TPR threads per row, rows i0 and i0 + 128 per thread,
+    //    every load of both rows in flight at once
+    if (upd && p.ymode == 0) {
+        const double *__restrict__ H = p.H + blk_hoff(tc, p.q, p.rem);
+        constexpr int HU = (MAXB + CSR_TPR - 1) / CSR_TPR;
+        constexpr int RPP = CSR_STEP_T / CSR_TPR;   // rows per pass (MAXB <= 2 * RPP)
+        static_assert(MAXB <= 2 * RPP, "two row slots per thread cover a block");
+        const int qd = tid % CSR_TPR, i0 = tid / CSR_TPR, i1 = i0 + RPP;
+        double h0[HU], h1[HU];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) {
+            const int j = qd + CSR_TPR * u;
+            h0[u] = (i0 < cnt && j < cnt) ? H[(int64_t)j * cnt + i0] : 0.0;
+            h1[u] = (i1 < cnt && j < cnt) ? H[(int64_t)j * cnt + i1] : 0.0;
+        }
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < HU; ++u) {
+            const int j = qd + CSR_TPR * u;
+            if (j < cnt) {
+                s0 = __builtin_fma(h0[u], s_r[j], s0);
+                s1 = __builtin_fma(h1[u], s_r[j], s1);
             }
-            acc = group_sum(acc, SPMV_LPR);
-            if (i < ncnt && sub == 0) p.Pout[i] = (double)acc;
+        }
+        s0 = group_sum(s0, CSR_TPR);
+        s1 = group_sum(s1, CSR_TPR);
+        if (qd == 0) {
+            if (i0 < cnt) s_y[i0] = s0;
+            if (i1 < cnt) s_y[i1] = s1;
+        }
+    }
+    __syncthreads();
+    if (upd && p.gb) {
+        V *gb = (V *)p.gb;
+        for (int i = tid; i < cnt; i += CSR_STEP_T) {
+            const int64_t row = (p.cur.kind == 1) ? (int64_t)p.cur.idx[i] : cst + i;
+            gb[row] -= (V)s_y[i];
+        }
+    }
+    // E. x += A_S^T y, chunk by chunk
+    if (upd) {
+        csr_apply_chunk<V>(x, ne0, s_y, e_col, e_val, e_row, e_slot, h_head, h_cnt, s_dup,
+                           &s_ndup);
+        for (int64_t base = CSR_CHUNK; base < tot; base += CSR_CHUNK) {
+            const int ne = (int)((tot - base < CSR_CHUNK) ? tot - base : CSR_CHUNK);
+            csr_clear_hash(h_key, h_head, h_cnt);
+            if (tid == 0) s_ndup = 0;
+            __syncthreads();
+            csr_stage_chunk<T, V>(p.colidx, val, s_off, s_p0, cnt, base, ne, e_col, e_val, e_row,
+                                  e_slot, h_key, h_head, h_cnt);
+            __syncthreads();
+            csr_apply_chunk<V>(x, ne, s_y, e_col, e_val, e_row, e_slot, h_head, h_cnt, s_dup,
+                               &s_ndup);
+        }
+    }
+    // F. products of the next rows with the updated x
+    if (ncnt > 0) {
+        if (npre) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int e = tid + u * CSR_STEP_T;
+                if (e < ntot) n_prod[e] = (V)nval[u] * x[ncol[u]];
+            }
+            __syncthreads();
+            for (int i = tid; i < ncnt; i += CSR_STEP_T) {
+                V acc = (V)0;
+                const int e1 = (int)n_off[i + 1];
+                for (int e = (int)n_off[i]; e < e1; ++e) acc = acc + n_prod[e];
+                p.Pout[i] = (double)acc;
+            }
+        } else {
+            const int sub = tid % SPMV_LPR;
+            for (int i0 = 0; i0 < ncnt; i0 += CSR_STEP_T / SPMV_LPR) {
+                const int i = i0 + tid / SPMV_LPR;
+                V acc = (V)0;
+                if (i < ncnt) {
+                    const int64_t e1 = n_p0[i] + n_len[i];
+                    for (int64_t pp = n_p0[i] + sub; pp < e1; pp += SPMV_LPR)
+                        acc = fmaT((V)val[pp], x[p.colidx[pp]], acc);
+                }
+                acc = group_sum(acc, SPMV_LPR);
+                if (i < ncnt && sub == 0) p.Pout[i] = (double)acc;
+            }
         }
     }
 }

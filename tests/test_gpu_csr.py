@@ -22,7 +22,10 @@ import paper_2510_02156_amd as P  # noqa: E402
 from tests.gpu_util import dev, host, rel  # noqa: E402
 
 # m, nnz per row (off-diagonal), block rows, lambda   (ragged partitions)
-CASES = [(3000, 12, 128, 1.28e-4), (2011, 12, 64, 1e-4), (1500, 5, 33, 1e-3), (900, 12, 129, 1e-3)]
+# the last case has more block entries than one update chunk or the next-row
+# prefetch holds (31 per row x 100 rows)
+CASES = [(3000, 12, 128, 1.28e-4), (2011, 12, 64, 1e-4), (1500, 5, 33, 1e-3), (900, 12, 129, 1e-3),
+         (1000, 30, 100, 1e-3)]
 
 
 def system(m, nnz_off, cfg=7, scale_lo=-6.0):
