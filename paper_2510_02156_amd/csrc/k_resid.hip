@@ -72,9 +72,12 @@ template <typename T, typename V, int ROWS>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
                               const void *x, double *axp, hipStream_t s) {
     const Layout &L = h->L;
-    // persistent grid: 2 workgroups (8 waves) per CU, fewer for short matrices
+    // persistent grid: 2 workgroups (8 waves) per CU over all segments, fewer
+    // for short matrices; with many segments (wide matrices) each wave keeps
+    // its slice of x for many rows
     int64_t groups = (L.m + 4 * ROWS - 1) / (4 * ROWS);
-    const int64_t cap = 2 * (int64_t)h->ncu;
+    int64_t cap = 2 * (int64_t)h->ncu / L.nseg;
+    if (cap < 1) cap = 1;
     if (groups > cap) groups = cap;
     dim3 grid((unsigned)groups, (unsigned)L.nseg);
     if (aligned)
