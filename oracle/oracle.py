@@ -75,6 +75,8 @@ def lib():
                                    C.c_int32, P, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_initial_solution.restype = C.c_int
+        L.orc_initial_solution.argtypes = [P, P, P, P]
         _lib = L
     return _lib
 
@@ -294,6 +296,19 @@ def backward(A, block_rows: int, mu: float, tau, Isets, iters: int,
     return gb, g
 
 
+def initial_solution(A, b):
+    """Algorithm 2 (appendix): x0 = (<b, A y> / ||A y||^2) y with y the sum of
+    the rows of A.  Returns (x0, coefficient)."""
+    M = _mat(A)
+    b = _f64(b)
+    x0 = np.zeros(M.n)
+    al = np.zeros(1)
+    rc = lib().orc_initial_solution(M.ptr, _p(b), _p(x0), _p(al))
+    if rc:
+        raise OracleError(rc, "initial_solution")
+    return x0, float(al[0])
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 
@@ -302,4 +317,4 @@ __all__ = ["ORC_OK", "ORC_ERR_ARG", "ORC_ERR_OOM", "ORC_ERR_NOT_SPD", "ORC_ERR_N
            "Matrix", "OracleError", "num_blocks", "partition", "cosine_rowsums",
            "proposal", "splitmix64_word", "sample", "sample_many", "cholesky",
            "chol_solve", "block_factor", "apply_block", "residual", "topk", "solve", "backward",
-           "num_threads", "lib"]
+           "initial_solution", "num_threads", "lib"]

@@ -622,6 +622,42 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------- initial solution (App.) */
+
+/* Algorithm 2 of the appendix (initial solution): y = the sum of all rows of
+ * A (each entry summed over the rows in ascending row order), b~ = A y, and
+ * x0 = (<b, b~> / ||b~||^2) y.  The remark after Algorithm 2: x0 lies in the
+ * row space of A and ||b - A x0|| <= ||b||.  When b~ = 0 the coefficient is 0
+ * (x0 = 0).  *alpha receives the coefficient. */
+int orc_initial_solution(const orc_matrix *A, const double *b, double *x0, double *alpha)
+{
+    const int64_t m = A->m, n = A->n;
+    double *y = (double *)calloc((size_t)n, sizeof(double));
+    double *bt = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!y || !bt) { free(y); free(bt); return ORC_ERR_OOM; }
+    for (int64_t i = 0; i < m; ++i) {
+        if (!A->csr) {
+            const double *ai = A->a + i * A->ld;
+            for (int64_t c = 0; c < n; ++c) y[c] += ai[c];
+        } else {
+            for (int64_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) y[A->colidx[p]] += A->val[p];
+        }
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i) bt[i] = row_dot(A, i, y);
+    double bb = 0.0, tt = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        bb += b[i] * bt[i];
+        tt += bt[i] * bt[i];
+    }
+    const double a = (tt > 0.0) ? bb / tt : 0.0;
+    for (int64_t c = 0; c < n; ++c) x0[c] = a * y[c];
+    if (alpha) *alpha = a;
+    free(y);
+    free(bt);
+    return ORC_OK;
+}
+
 /* Number of threads OpenMP will use (reported with the CPU timings). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -509,3 +509,51 @@ def test_adjoint_finite_differences(rng):
         e = np.zeros(n); e[i] = h
         fd = (loss(b, x0 + e) - loss(b, x0 - e)) / (2 * h)
         assert fd == pytest.approx(gx0[i], rel=1e-7, abs=1e-9)
+
+
+# ------------------------------------------------ Algorithm 2 (initial solution)
+
+def test_initial_solution_identity_closed_form():
+    """A = I: the row sum is the all-ones vector, A y = 1, so x0 = mean(b) 1."""
+    n = 37
+    b = np.random.default_rng(4).standard_normal(n)
+    x0, a = O.initial_solution(np.eye(n), b)
+    assert a == pytest.approx(b.mean(), rel=1e-14)
+    np.testing.assert_allclose(x0, np.full(n, b.mean()), rtol=1e-13)
+
+
+def test_initial_solution_remark_properties():
+    """The remark after Algorithm 2: x0 in R(A^T) and RRN(x0) <= 1; from its
+    proof, RRN(x0)^2 = 1 - <b, A y>^2 / (||b||^2 ||A y||^2) and the residual is
+    orthogonal to A y."""
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((40, 90)) + 0.3      # wide: a null space exists
+    b = rng.standard_normal(40)
+    x0, a = O.initial_solution(A, b)
+    r = b - A @ x0
+    rrn = np.linalg.norm(r) / np.linalg.norm(b)
+    assert rrn <= 1.0
+    bt = A @ A.sum(axis=0)
+    cos2 = (b @ bt) ** 2 / ((b @ b) * (bt @ bt))
+    assert rrn ** 2 == pytest.approx(1.0 - cos2, rel=1e-10)
+    assert abs(r @ bt) <= 1e-10 * np.linalg.norm(r) * np.linalg.norm(bt)
+    coef = np.linalg.lstsq(A.T, x0, rcond=None)[0]          # x0 = A^T coef exactly?
+    assert np.linalg.norm(A.T @ coef - x0) <= 1e-12 * np.linalg.norm(x0)
+
+
+def test_initial_solution_degenerate_row_sum():
+    """Rows that sum to zero give y = 0 and A y = 0: the coefficient is 0."""
+    rng = np.random.default_rng(2)
+    B = rng.integers(-9, 10, size=(10, 6)).astype(np.float64)   # exact sums
+    A = np.vstack([B, -B])
+    x0, a = O.initial_solution(A, rng.standard_normal(20))
+    assert a == 0.0 and not np.any(x0)
+
+
+def test_initial_solution_csr_matches_dense():
+    s = csr_system(300, 5, cfg=5)
+    x0c, ac = O.initial_solution(s, s["b"])
+    D = O.Matrix(s).dense()
+    x0d, ad = O.initial_solution(D, s["b"])
+    assert ac == pytest.approx(ad, rel=1e-12)
+    np.testing.assert_allclose(x0c, x0d, rtol=1e-12, atol=1e-300)
