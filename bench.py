@@ -213,6 +213,13 @@ def main():
                                     "fp64": float(s64.residual(b, x64)[2])}
         res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
                                    "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
+        # Algorithm 2's starting iterate (one product pass over A in FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x0i, coef = s64.initial_solution(b)
+        torch.cuda.synchronize()
+        res["initial_solution"] = {"ms": (time.perf_counter() - t0) * 1e3, "coefficient": coef,
+                                   "rrn_x0": float(s64.residual(b, x0i)[2])}
         if not csr:
             # the other 16-/32-bit storage beside the one timed as `value`
             other = "bf16" if args.mixed == "f32" else "f32"

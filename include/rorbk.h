@@ -187,6 +187,17 @@ int ror_bk_get_record(rorbk_handle h, int32_t *tau_host, int32_t *I_host,
 int ror_bk_set_replay(rorbk_handle h, const int32_t *tau_host,
                       const int32_t *I_host, int64_t iters);
 
+/* Initial solution (appendix, Algorithm 2, and the remark after it):
+ * x0 = (<b, A y> / ||A y||^2) y with y the sum of all rows of A (kept from the
+ * setup: the block row-sums added in block order), so that x0 lies in the row
+ * space of A and ||b - A x0|| <= ||b||; x0 = 0 if A y = 0.  b (device, m) and
+ * x0 (device, n, written) have the vector type given by vec_f32 (0: double,
+ * with the FP64 master copy for F32/BF16 storage; 1: float, F32/BF16 storage
+ * only).  coef_host (may be NULL) receives the coefficient; the stream is
+ * synchronised only then.  Pass x0 as the starting iterate of ror_bk_solve. */
+int ror_bk_initial_solution(rorbk_handle h, const void *b, void *x0, int32_t vec_f32,
+                            double *coef_host);
+
 /* Refinement controls for RORBK_REFINE: inner iterations per FP64 correction
  * (default 50) and the inner relative stop eta (default 1e-4; the inner solve
  * also stops once its residual is below tol * ||b||). */

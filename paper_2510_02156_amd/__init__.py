@@ -14,7 +14,7 @@ from .binding import (RORBK_CHECKPOINT, RORBK_PROFILE, RORBK_RECORD, RORBK_REFIN
                       RorBkError, lib, ror_bk_backward, ror_bk_destroy,
                       ror_bk_get_block_inverse, ror_bk_get_profile, ror_bk_get_record,
                       ror_bk_get_setup,
-                      ror_bk_get_sizes, ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
+                      ror_bk_get_sizes, ror_bk_initial_solution, ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
                       ror_bk_set_refine, ror_bk_set_replay, ror_bk_setup, ror_bk_solve,
                       ror_bk_topk)
 
@@ -89,6 +89,13 @@ class Solver:
         bn = torch.empty(self.k, dtype=torch.float64, device=b.device)
         rrn = ror_bk_residual(self.h, b, x, r, bn, use_f64_master)
         return r, bn, rrn
+
+    def initial_solution(self, b):
+        """Algorithm 2's starting iterate for b (same vector type as b);
+        returns (x0, coefficient)."""
+        x0 = torch.empty(self.n, dtype=b.dtype, device=b.device)
+        coef = ror_bk_initial_solution(self.h, b, x0)
+        return x0, coef
 
     def profile(self) -> dict:
         return ror_bk_get_profile(self.h)

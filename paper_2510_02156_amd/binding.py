@@ -35,7 +35,8 @@ EXPORTS = [
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
     "ror_bk_get_block_inverse", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
     "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
-    "ror_bk_get_profile", "ror_bk_error_string", "ror_bk_last_error_message",
+    "ror_bk_get_profile", "ror_bk_initial_solution", "ror_bk_error_string",
+    "ror_bk_last_error_message",
 ]
 
 
@@ -95,6 +96,7 @@ def lib():
             "ror_bk_set_replay": (C.c_int, [P, P, P, I64]),
             "ror_bk_set_refine": (C.c_int, [P, I64, D]),
             "ror_bk_get_profile": (C.c_int, [P, P]),
+            "ror_bk_initial_solution": (C.c_int, [P, P, P, I32, P]),
             "ror_bk_error_string": (C.c_char_p, [C.c_int]),
             "ror_bk_last_error_message": (C.c_char_p, []),
         }
@@ -254,6 +256,15 @@ def ror_bk_get_record(h, K: int):
     got_I = lib().ror_bk_get_record(h, None, _np_ptr(I), None, C.byref(it))
     return {"iters": n, "tau": tau, "rrn": rrn,
             "I": I.reshape(n, K) if got_I == RORBK_OK else None}
+
+
+def ror_bk_initial_solution(h, b, x0) -> float:
+    """Algorithm 2's x0 into x0 (vector type of b); returns the coefficient."""
+    vec_f32 = 1 if str(b.dtype) == "torch.float32" else 0
+    coef = C.c_double()
+    _check(lib().ror_bk_initial_solution(h, _dev_ptr(b), _dev_ptr(x0), vec_f32, C.byref(coef)),
+           "ror_bk_initial_solution")
+    return coef.value
 
 
 def ror_bk_set_replay(h, tau, I, iters: int):

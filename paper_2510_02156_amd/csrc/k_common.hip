@@ -945,6 +945,75 @@ hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ initial solution --
+// Algorithm 2 (appendix): y = the sum of the rows of A, kept from the setup as
+// the sum of the block row-sums (centroids) in block order.
+__global__ __launch_bounds__(256) void k_colsum(const double *__restrict__ cen, int64_t k,
+                                                int64_t n, double *__restrict__ y) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int64_t t = 0; t < k; ++t) s += cen[t * n + j];
+    y[j] = s;
+}
+
+// The coefficient <b, b~> / ||b~||^2 of Algorithm 2 with b~ = A y given as the
+// residual pass's segment products (summed in segment order): per-thread sums
+// over a contiguous run of rows, then a fixed-order workgroup sum.
+// out[0] = <b, b~>, out[1] = ||b~||^2, out[2] = the coefficient (0 if b~ = 0).
+template <typename V>
+__global__ __launch_bounds__(1024) void k_alg2_coef(const V *__restrict__ b,
+                                                    const double *__restrict__ axp, int nseg,
+                                                    int64_t m, double *__restrict__ out) {
+    __shared__ double sh[16];
+    const int64_t per = (m + blockDim.x - 1) / blockDim.x;
+    const int64_t a = threadIdx.x * per, e = (a + per < m) ? a + per : m;
+    double sb = 0.0, st = 0.0;
+    for (int64_t i = a; i < e; ++i) {
+        double bt = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) bt += axp[(int64_t)sg * m + i];
+        sb = __builtin_fma((double)b[i], bt, sb);
+        st = __builtin_fma(bt, bt, st);
+    }
+    sb = block_sum(sb, sh);
+    st = block_sum(st, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sb;
+        out[1] = st;
+        out[2] = (st > 0.0) ? sb / st : 0.0;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_scale_vec(const double *__restrict__ y,
+                                                   const double *__restrict__ coef,
+                                                   V *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (V)(coef[0] * y[i]);
+}
+
+hipError_t launch_colsum(const double *cen, int64_t k, int64_t n, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cen, k, n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_alg2(const void *b, int vec, const double *axp, int nseg, int64_t m,
+                       const double *y, double *coef, void *x, int64_t n, hipStream_t s) {
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (vec == VEC_F64) {
+        hipLaunchKernelGGL(k_alg2_coef<double>, dim3(1), dim3(1024), 0, s, (const double *)b, axp,
+                           nseg, m, coef);
+        hipLaunchKernelGGL(k_scale_vec<double>, dim3(g), dim3(256), 0, s, y, coef + 2,
+                           (double *)x, n);
+    } else {
+        hipLaunchKernelGGL(k_alg2_coef<float>, dim3(1), dim3(1024), 0, s, (const float *)b, axp,
+                           nseg, m, coef);
+        hipLaunchKernelGGL(k_scale_vec<float>, dim3(g), dim3(256), 0, s, y, coef + 2,
+                           (float *)x, n);
+    }
+    return hipGetLastError();
+}
+
 // -------------------------------------------------------- refinement glue --
 __global__ void k_cast_f64_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -621,6 +621,8 @@ hipError_t launch_setup_proposal_csr(const rorbk_handle_s *h, const void *vals, 
                            h->colidx, (const float *)vals, L.n, L.q, L.rem, cen);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    e = launch_colsum(cen, L.k, L.n, h->d_ysum, s);     // the row sum of A (Algorithm 2)
+    if (e != hipSuccess) return e;
     return launch_proposal_from_centroids(h, cen, nrm, Sp, s);
 }
 

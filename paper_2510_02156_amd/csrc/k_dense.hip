@@ -499,6 +499,8 @@ hipError_t launch_setup_proposal_dense(const rorbk_handle_s *h, const void *A, i
                            L.ld, L.n, L.q, L.rem, cen);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    e = launch_colsum(cen, L.k, L.n, h->d_ysum, s);     // the row sum of A (Algorithm 2)
+    if (e != hipSuccess) return e;
     return launch_proposal_from_centroids(h, cen, nrm, Sp, s);
 }
 

@@ -136,6 +136,9 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_G);
     dfree(h->d_red);
     dfree(h->d_selcnt);
+    dfree(h->d_ysum);
+    dfree(h->d_ysum32);
+    dfree(h->d_alg2);
     dfree(h->d_rhs32);
     dfree(h->d_d32);
     dfree(h->d_r64);
@@ -504,6 +507,8 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_G, (int64_t)L.nch_g * K * (K + 1) / 2);
     ALLOC(h->d_red, 64);
     ALLOC(h->d_selcnt, 1);
+    ALLOC(h->d_ysum, L.n);
+    ALLOC(h->d_alg2, 3);
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_ctrl, 3 * sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -706,6 +711,39 @@ int ror_bk_residual(rorbk_handle h, const void *b, const void *x, void *r, doubl
     const Ctrl &c = *h->h_ctrl;
     if (rrn_host) *rrn_host = c.bnorm2 > 0 ? std::sqrt(c.rnorm2 / c.bnorm2) : 0.0;
     if (c.status) return fail(c.status, "non-finite residual");
+    return RORBK_OK;
+}
+
+int ror_bk_initial_solution(rorbk_handle h, const void *b, void *x0, int32_t vec_f32,
+                            double *coef_host) {
+    if (!h || !b || !x0) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
+    g_msg[0] = 0;
+    const Layout &L = h->L;
+    const int vec = vec_f32 ? VEC_F32 : VEC_F64;
+    const void *A = h->A;
+    int dt = L.dtype, al = h->aligned;
+    if (vec == VEC_F64 && L.dtype != RORBK_F64) {
+        if (!h->A64) return fail(RORBK_ERR_INVALID_ARG, "FP64 vectors need the FP64 master copy");
+        A = h->A64;
+        dt = RORBK_F64;
+        al = h->aligned64;
+    }
+    if (vec == VEC_F32 && dt == RORBK_F64)
+        return fail(RORBK_ERR_INVALID_ARG, "float vectors need F32 or BF16 storage");
+    const void *yv = h->d_ysum;
+    if (vec == VEC_F32) {
+        if (!h->d_ysum32) CHK(dalloc(&h->d_ysum32, (size_t)L.n));
+        HIPCHK(launch_cast_f64_to_f32(h->d_ysum, h->d_ysum32, L.n, h->stream));
+        yv = h->d_ysum32;
+    }
+    HIPCHK(hipMemsetAsync(h->d_ctrl, 0, sizeof(Ctrl), h->stream));   // the product pass runs
+    HIPCHK(residual(h, A, dt, al, vec, yv, h->d_axp));
+    HIPCHK(launch_alg2(b, vec, h->d_axp, L.nseg, L.m, h->d_ysum, h->d_alg2, x0, L.n, h->stream));
+    if (coef_host) {
+        HIPCHK(hipMemcpyAsync(coef_host, h->d_alg2 + 2, sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
     return RORBK_OK;
 }
 

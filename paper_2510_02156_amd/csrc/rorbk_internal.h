@@ -77,6 +77,9 @@ struct rorbk_handle_s {
     rorbk::Ctrl *d_ctrl;
     rorbk::Ctrl *h_ctrl;      // pinned mirror
     uint32_t *d_selcnt;       // selection workgroups done (fused merge), 0 between launches
+    double *d_ysum;           // sum of the rows of A (n), for the initial solution
+    float *d_ysum32;          // the same in FP32 (allocated on first use)
+    double *d_alg2;           // <b, A y>, ||A y||^2, coefficient
     double *d_P[2];           // partial A_S x per update chunk [nch][bmax]
     double *d_axp;            // residual partial products [nseg][m]
     void *d_r;                // residual (vector type)
@@ -215,6 +218,11 @@ hipError_t launch_set_refine_ctrl(Ctrl *c, double tol, double eta,
 hipError_t launch_init_ctrl(Ctrl *c, double tol, const double *bnorm2, hipStream_t s);
 hipError_t launch_set_thr(Ctrl *c, double thr, hipStream_t s);
 hipError_t launch_axpy_f64(const double *d, double *x, int64_t n, hipStream_t s);
+// initial solution (Algorithm 2): y = column sums of the k x n centroids
+hipError_t launch_colsum(const double *cen, int64_t k, int64_t n, double *y, hipStream_t s);
+// coefficient from b and the products A y (axp), then x = coefficient * y
+hipError_t launch_alg2(const void *b, int vec, const double *axp, int nseg, int64_t m,
+                       const double *y, double *coef, void *x, int64_t n, hipStream_t s);
 
 // format-specific block step, residual products and greedy Gram
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
