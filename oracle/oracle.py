@@ -75,6 +75,9 @@ def lib():
                                    C.c_int32, P, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_fabgmres.restype = C.c_int
+        L.orc_fabgmres.argtypes = [P, C.c_int64, C.c_double, P, P, C.c_uint64, C.c_double,
+                                   C.c_int64, C.c_int64, C.c_double, P, P, P, P, P]
         L.orc_initial_solution.restype = C.c_int
         L.orc_initial_solution.argtypes = [P, P, P, P]
         _lib = L
@@ -309,6 +312,32 @@ def initial_solution(A, b):
     return x0, float(al[0])
 
 
+def fabgmres(A, block_rows: int, mu: float, b, x0=None, seed: int = 0, tol: float = 1e-8,
+             max_outer: int = 20, inner_iters: int = 10, eta: float = 1e-1, W=None,
+             want_basis: bool = False) -> dict:
+    """Algorithm 3 (appendix) in FP64: flexible AB-GMRES with ROR-BK inner
+    iterations.  Returns x, the outer steps taken and the residual estimates;
+    with want_basis also Z (n x max_outer) and H ((max_outer+1) x max_outer)."""
+    M = _mat(A)
+    b = _f64(b)
+    x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
+    Wa = None if W is None else _f64(W)
+    outer = np.zeros(1, dtype=np.int64)
+    hist = np.zeros(max_outer)
+    Z = np.zeros((max_outer, M.n)) if want_basis else None
+    H = np.zeros((max_outer, max_outer + 1)) if want_basis else None
+    rc = lib().orc_fabgmres(M.ptr, block_rows, mu, _p(b), _p(x), seed & ((1 << 64) - 1), tol,
+                            max_outer, inner_iters, eta, _p(Wa), _p(outer), _p(hist), _p(Z), _p(H))
+    if rc:
+        raise OracleError(rc, "fabgmres")
+    k = int(outer[0])
+    out = {"x": x, "outer": k, "res_hist": hist[:k].copy()}
+    if want_basis:
+        out["Z"] = Z[:k].T.copy()                 # n x k
+        out["H"] = H[:k, :k + 1].T.copy()          # (k+1) x k
+    return out
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 
@@ -317,4 +346,4 @@ __all__ = ["ORC_OK", "ORC_ERR_ARG", "ORC_ERR_OOM", "ORC_ERR_NOT_SPD", "ORC_ERR_N
            "Matrix", "OracleError", "num_blocks", "partition", "cosine_rowsums",
            "proposal", "splitmix64_word", "sample", "sample_many", "cholesky",
            "chol_solve", "block_factor", "apply_block", "residual", "topk", "solve", "backward",
-           "initial_solution", "num_threads", "lib"]
+           "initial_solution", "fabgmres", "num_threads", "lib"]

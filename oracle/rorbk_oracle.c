@@ -658,6 +658,128 @@ int orc_initial_solution(const orc_matrix *A, const double *b, double *x0, doubl
     return ORC_OK;
 }
 
+/* ------------------------------------ flexible AB-GMRES (App., Algorithm 3) */
+
+/* Algorithm 3 of the appendix: flexible AB-GMRES with ROR-BK as the right
+ * preconditioner.  From x (x0 in, result out): r0 = b - A x0, beta = ||r0||,
+ * v_1 = r0 / beta.  Outer step k: z_k = ROR-BK (Algorithm 1) on A z = v_k from
+ * z = 0 for at most inner_iters iterations, stopping once ||v_k - A z|| <
+ * eta ||v_k||; its sampler counter starts at (k - 1) * inner_iters, so every
+ * outer step draws fresh blocks from the same stream.  w = A z_k is
+ * orthogonalised against v_1..v_k by modified Gram-Schmidt (h_ik = <w, v_i>,
+ * w -= h_ik v_i), h_{k+1,k} = ||w||, v_{k+1} = w / h_{k+1,k}.  The Hessenberg
+ * least-squares problem min ||beta e_1 - H y|| is kept reduced with Givens
+ * rotations; the outer loop stops when its residual |g_{k+1}| < tol ||b||,
+ * when h_{k+1,k} = 0, or after max_outer steps.  Then x = x0 + Z y.
+ * W: the sampler's running sums (NULL: computed here).  Outputs: *outer
+ * steps taken, res_hist[k] = |g_{k+1}| / ||b|| per step, and (optional) Z
+ * (n x max_outer, column k at Z + k n) and H ((max_outer + 1) x max_outer,
+ * column-major, before the rotations). */
+int orc_fabgmres(const orc_matrix *A, int64_t block_rows, double mu, const double *b,
+                 double *x, uint64_t seed, double tol, int64_t max_outer, int64_t inner_iters,
+                 double eta, const double *W_in, int64_t *outer, double *res_hist, double *Zout,
+                 double *Hout)
+{
+    const int64_t m = A->m, n = A->n;
+    const int64_t kb = orc_num_blocks(m, block_rows);
+    if (kb <= 0 || max_outer < 1 || inner_iters < 1) return ORC_ERR_ARG;
+    const int64_t M1 = max_outer + 1;
+    double *V = (double *)malloc(sizeof(double) * (size_t)(m * M1));
+    double *Z = (double *)calloc((size_t)(n * max_outer), sizeof(double));
+    double *H = (double *)calloc((size_t)(M1 * max_outer), sizeof(double));
+    double *R = (double *)calloc((size_t)(M1 * max_outer), sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * (size_t)max_outer);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)max_outer);
+    double *g = (double *)calloc((size_t)M1, sizeof(double));
+    double *w = (double *)malloc(sizeof(double) * (size_t)m);
+    double *W = (double *)malloc(sizeof(double) * (size_t)kb);
+    double *yv = (double *)calloc((size_t)max_outer, sizeof(double));
+    int rc = ORC_OK;
+    if (!V || !Z || !H || !R || !cs || !sn || !g || !w || !W || !yv) { rc = ORC_ERR_OOM; goto done; }
+    if (W_in) {
+        memcpy(W, W_in, sizeof(double) * (size_t)kb);
+    } else {
+        int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(kb + 1));
+        double *S = (double *)malloc(sizeof(double) * (size_t)kb);
+        double *pb = (double *)malloc(sizeof(double) * (size_t)kb);
+        if (!off || !S || !pb) { free(off); free(S); free(pb); rc = ORC_ERR_OOM; goto done; }
+        orc_partition(m, kb, off);
+        rc = orc_cosine_rowsums(A, kb, off, 0, kb, S);
+        if (!rc) orc_proposal(S, kb, n, pb, W);
+        free(off); free(S); free(pb);
+        if (rc) goto done;
+    }
+    double bn = 0.0;
+    for (int64_t i = 0; i < m; ++i) bn += b[i] * b[i];
+    bn = sqrt(bn);
+    orc_residual(A, b, x, w);
+    double beta = 0.0;
+    for (int64_t i = 0; i < m; ++i) beta += w[i] * w[i];
+    beta = sqrt(beta);
+    *outer = 0;
+    if (beta == 0.0) goto done;
+    for (int64_t i = 0; i < m; ++i) V[i] = w[i] / beta;
+    g[0] = beta;
+    int64_t kend = 0;
+    for (int64_t k = 0; k < max_outer; ++k) {
+        /* z_k: inner ROR-BK on A z = v_k from zero */
+        double *zk = Z + k * n;
+        int64_t ints[2];
+        double rrn, times[2];
+        rc = orc_solve(A, block_rows, mu, V + k * m, zk, seed, eta, inner_iters,
+                       k * inner_iters, W, NULL, NULL, NULL, NULL, NULL, ints, &rrn, times);
+        if (rc) goto done;
+        /* w = A z_k, modified Gram-Schmidt against v_1..v_k */
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < m; ++i) w[i] = row_dot(A, i, zk);
+        for (int64_t i2 = 0; i2 <= k; ++i2) {
+            const double *vi = V + i2 * m;
+            double h = 0.0;
+            for (int64_t i = 0; i < m; ++i) h += w[i] * vi[i];
+            for (int64_t i = 0; i < m; ++i) w[i] -= h * vi[i];
+            H[k * M1 + i2] = h;
+        }
+        double hn = 0.0;
+        for (int64_t i = 0; i < m; ++i) hn += w[i] * w[i];
+        hn = sqrt(hn);
+        H[k * M1 + k + 1] = hn;
+        if (hn > 0.0)
+            for (int64_t i = 0; i < m; ++i) V[(k + 1) * m + i] = w[i] / hn;
+        /* Givens: earlier rotations on column k, then a new one */
+        for (int64_t i2 = 0; i2 <= k + 1; ++i2) R[k * M1 + i2] = H[k * M1 + i2];
+        for (int64_t i2 = 0; i2 < k; ++i2) {
+            const double a = R[k * M1 + i2], c = R[k * M1 + i2 + 1];
+            R[k * M1 + i2] = cs[i2] * a + sn[i2] * c;
+            R[k * M1 + i2 + 1] = -sn[i2] * a + cs[i2] * c;
+        }
+        const double a = R[k * M1 + k], c = R[k * M1 + k + 1];
+        const double d = sqrt(a * a + c * c);
+        cs[k] = (d > 0.0) ? a / d : 1.0;
+        sn[k] = (d > 0.0) ? c / d : 0.0;
+        R[k * M1 + k] = d;
+        R[k * M1 + k + 1] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        if (res_hist) res_hist[k] = fabs(g[k + 1]) / (bn > 0.0 ? bn : 1.0);
+        kend = k + 1;
+        if (fabs(g[k + 1]) < tol * bn || hn == 0.0) break;
+    }
+    /* R y = g (upper triangular), x = x0 + Z y */
+    for (int64_t i2 = kend - 1; i2 >= 0; --i2) {
+        double s2 = g[i2];
+        for (int64_t j = i2 + 1; j < kend; ++j) s2 -= R[j * M1 + i2] * yv[j];
+        yv[i2] = s2 / R[i2 * M1 + i2];
+    }
+    for (int64_t j = 0; j < kend; ++j)
+        for (int64_t c2 = 0; c2 < n; ++c2) x[c2] += yv[j] * Z[j * n + c2];
+    *outer = kend;
+    if (Zout) memcpy(Zout, Z, sizeof(double) * (size_t)(n * max_outer));
+    if (Hout) memcpy(Hout, H, sizeof(double) * (size_t)(M1 * max_outer));
+done:
+    free(V); free(Z); free(H); free(R); free(cs); free(sn); free(g); free(w); free(W); free(yv);
+    return rc;
+}
+
 /* Number of threads OpenMP will use (reported with the CPU timings). */
 #ifdef _OPENMP
 #include <omp.h>

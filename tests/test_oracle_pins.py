@@ -557,3 +557,52 @@ def test_initial_solution_csr_matches_dense():
     x0d, ad = O.initial_solution(D, s["b"])
     assert ac == pytest.approx(ad, rel=1e-12)
     np.testing.assert_allclose(x0c, x0d, rtol=1e-12, atol=1e-300)
+
+
+# ------------------------------------------- Algorithm 3 (flexible AB-GMRES)
+
+def test_fabgmres_least_squares_property():
+    """x_k = x0 + Z y with y minimising ||r0 - A Z y|| over the returned
+    preconditioned directions, the rotated residual |g_{k+1}| equals the true
+    ||b - A x_k||, and GMRES residuals never increase."""
+    s = dense_svd_system(300, 120, 1e3, cfg=61)
+    A, b = s["A"], s["b"]
+    out = O.fabgmres(A, 20, 1e-3, b, seed=2, tol=1e-14, max_outer=12, inner_iters=3, eta=1e-6,
+                     want_basis=True)
+    k = out["outer"]
+    assert k == 12
+    Z = out["Z"]
+    y = np.linalg.lstsq(A @ Z, b, rcond=None)[0]
+    best = np.linalg.norm(b - A @ (Z @ y))
+    got = np.linalg.norm(b - A @ out["x"])
+    assert got == pytest.approx(best, rel=1e-8)
+    assert out["res_hist"][-1] * np.linalg.norm(b) == pytest.approx(got, rel=1e-7)
+    assert np.all(np.diff(out["res_hist"]) <= 1e-12)
+    H = out["H"]
+    assert np.all(np.abs(np.tril(H, -2)) == 0.0) and np.all(np.diag(H, -1) >= 0.0)
+
+
+def test_fabgmres_row_space():
+    """The remark after Algorithm 3: from x0 = 0 (and inner z0 = 0) the result
+    lies in the row space of A."""
+    s = dense_svd_system(60, 200, 1e2, cfg=62, rowspace=True)
+    A = s["A"]
+    out = O.fabgmres(A, 10, 1e-4, s["b"], seed=4, tol=1e-12, max_outer=8, inner_iters=2, eta=1e-8)
+    x = out["x"]
+    null = x - A.T @ np.linalg.solve(A @ A.T, A @ x)
+    assert np.linalg.norm(null) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_fabgmres_exact_inner_solve_one_step():
+    """One block of all rows: the inner ROR-BK step is the regularised
+    pseudo-inverse A^T (A A^T + mu I)^{-1} v, so A z = v up to mu and the
+    outer residual after one step is of the order of mu."""
+    rng = np.random.default_rng(63)
+    A = rng.standard_normal((40, 90))
+    b = rng.standard_normal(40)
+    mu = 1e-9
+    out = O.fabgmres(A, 40, mu, b, seed=0, tol=1e-30, max_outer=1, inner_iters=1, eta=0.0)
+    z = A.T @ np.linalg.solve(A @ A.T + mu * np.eye(40), b / np.linalg.norm(b))
+    scale = np.linalg.norm(b) / np.linalg.norm(A @ z) ** 2 * (b @ (A @ z)) / np.linalg.norm(b)
+    np.testing.assert_allclose(out["x"], scale * z, rtol=1e-8)
+    assert out["res_hist"][0] < 1e-6
