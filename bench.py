@@ -213,6 +213,23 @@ def main():
                                     "fp64": float(s64.residual(b, x64)[2])}
         res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
                                    "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
+        # Algorithm 3: flexible AB-GMRES with ROR-BK inner iterations (FP64),
+        # against plain ROR-BK run for the same number of inner iterations
+        outer, inner = 30, 20
+        xg = torch.zeros(n, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xg, ig = s64.fabgmres(b, xg, seed=seed, tol=tol, max_outer=outer, inner_iters=inner,
+                              eta=1e-2)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        _, i_eq, t_eq = run(s64, False, max(ig["inner_iters"], 1))
+        res["fabgmres"] = {"time_s": tg, "outer": ig["outer"], "inner_iters": ig["inner_iters"],
+                           "rrn": ig["rrn"], "max_outer": outer, "inner_per_outer": inner,
+                           "eta": 1e-2,
+                           "plain_rorbk_same_iters": {"time_s": t_eq, "rrn": i_eq["rrn"]}}
+        log(f"fabgmres: {tg:.3f}s, {ig['outer']} outer / {ig['inner_iters']} inner, "
+            f"rrn {ig['rrn']:.3e} (plain ROR-BK same iterations: rrn {i_eq['rrn']:.3e})")
         # Algorithm 2's starting iterate (one product pass over A in FP64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

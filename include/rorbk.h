@@ -187,6 +187,22 @@ int ror_bk_get_record(rorbk_handle h, int32_t *tau_host, int32_t *I_host,
 int ror_bk_set_replay(rorbk_handle h, const int32_t *tau_host,
                       const int32_t *I_host, int64_t iters);
 
+/* Flexible AB-GMRES with ROR-BK as the right preconditioner (appendix,
+ * Algorithm 3, and the remark on it in Section 2).  FP64 storage; b (device,
+ * m doubles), x (device, n doubles: x0 in, result out).  From r0 = b - A x0:
+ * outer step k runs ROR-BK (Algorithm 1, this handle's setup) on A z = v_k
+ * from z = 0 for at most inner_iters iterations, stopping once
+ * ||v_k - A z|| < eta ||v_k|| (draws from words of the seed's stream starting
+ * at iteration k * inner_iters), orthogonalises w = A z_k against v_1..v_k by
+ * modified Gram-Schmidt, and reduces the Hessenberg least-squares problem with
+ * Givens rotations; it stops when that problem's residual is below
+ * tol * ||b||, on breakdown, or after max_outer steps; then x = x0 + Z y.
+ * info (may be NULL): iters = inner iterations in total, n_refine = outer
+ * steps, converged, rrn = ||b - A x|| / ||b|| of the result.  Workspaces of
+ * (m + n) * (max_outer + 1) doubles are allocated for the call. */
+int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, double tol,
+                    int64_t max_outer, int64_t inner_iters, double eta, rorbk_info *info);
+
 /* Initial solution (appendix, Algorithm 2, and the remark after it):
  * x0 = (<b, A y> / ||A y||^2) y with y the sum of all rows of A (kept from the
  * setup: the block row-sums added in block order), so that x0 lies in the row

@@ -14,7 +14,8 @@ from .binding import (RORBK_CHECKPOINT, RORBK_PROFILE, RORBK_RECORD, RORBK_REFIN
                       RorBkError, lib, ror_bk_backward, ror_bk_destroy,
                       ror_bk_get_block_inverse, ror_bk_get_profile, ror_bk_get_record,
                       ror_bk_get_setup,
-                      ror_bk_get_sizes, ror_bk_initial_solution, ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
+                      ror_bk_fabgmres, ror_bk_get_sizes, ror_bk_initial_solution,
+                      ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
                       ror_bk_set_refine, ror_bk_set_replay, ror_bk_setup, ror_bk_solve,
                       ror_bk_topk)
 
@@ -89,6 +90,17 @@ class Solver:
         bn = torch.empty(self.k, dtype=torch.float64, device=b.device)
         rrn = ror_bk_residual(self.h, b, x, r, bn, use_f64_master)
         return r, bn, rrn
+
+    def fabgmres(self, b, x=None, *, seed: int = 0, tol: float = 1e-8, max_outer: int = 20,
+                 inner_iters: int = 10, eta: float = 1e-1):
+        """Flexible AB-GMRES with ROR-BK inner iterations (FP64 storage) from x
+        (zeros if None; updated in place).  Returns (x, info)."""
+        if x is None:
+            x = torch.zeros(self.n, dtype=torch.float64, device=b.device)
+        if b.dtype != torch.float64 or x.dtype != torch.float64:
+            raise TypeError("flexible AB-GMRES works on double vectors")
+        info = ror_bk_fabgmres(self.h, b, x, seed, tol, max_outer, inner_iters, eta)
+        return x, info
 
     def initial_solution(self, b):
         """Algorithm 2's starting iterate for b (same vector type as b);

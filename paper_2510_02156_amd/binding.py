@@ -35,7 +35,7 @@ EXPORTS = [
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
     "ror_bk_get_block_inverse", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
     "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
-    "ror_bk_get_profile", "ror_bk_initial_solution", "ror_bk_error_string",
+    "ror_bk_get_profile", "ror_bk_initial_solution", "ror_bk_fabgmres", "ror_bk_error_string",
     "ror_bk_last_error_message",
 ]
 
@@ -97,6 +97,8 @@ def lib():
             "ror_bk_set_refine": (C.c_int, [P, I64, D]),
             "ror_bk_get_profile": (C.c_int, [P, P]),
             "ror_bk_initial_solution": (C.c_int, [P, P, P, I32, P]),
+            "ror_bk_fabgmres": (C.c_int, [P, P, P, C.c_uint64, D, I64, I64, D,
+                                          C.POINTER(rorbk_info)]),
             "ror_bk_error_string": (C.c_char_p, [C.c_int]),
             "ror_bk_last_error_message": (C.c_char_p, []),
         }
@@ -265,6 +267,16 @@ def ror_bk_initial_solution(h, b, x0) -> float:
     _check(lib().ror_bk_initial_solution(h, _dev_ptr(b), _dev_ptr(x0), vec_f32, C.byref(coef)),
            "ror_bk_initial_solution")
     return coef.value
+
+
+def ror_bk_fabgmres(h, b, x, seed: int, tol: float, max_outer: int, inner_iters: int,
+                    eta: float) -> dict:
+    info = rorbk_info()
+    _check(lib().ror_bk_fabgmres(h, _dev_ptr(b), _dev_ptr(x), seed & ((1 << 64) - 1), float(tol),
+                                 int(max_outer), int(inner_iters), float(eta), C.byref(info)),
+           "ror_bk_fabgmres")
+    return {"inner_iters": info.iters, "outer": info.n_refine, "converged": bool(info.converged),
+            "rrn": info.rrn}
 
 
 def ror_bk_set_replay(h, tau, I, iters: int):

@@ -714,6 +714,130 @@ int ror_bk_residual(rorbk_handle h, const void *b, const void *x, void *r, doubl
     return RORBK_OK;
 }
 
+int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, double tol,
+                    int64_t max_outer, int64_t inner_iters, double eta, rorbk_info *info) {
+    g_msg[0] = 0;
+    if (!h || !b || !x) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
+    if (max_outer < 1 || inner_iters < 1)
+        return fail(RORBK_ERR_INVALID_ARG, "max_outer and inner_iters must be >= 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol) || !(eta >= 0.0) || !std::isfinite(eta))
+        return fail(RORBK_ERR_INVALID_ARG, "tol and eta must be finite and >= 0");
+    const Layout &L = h->L;
+    if (L.dtype != RORBK_F64)
+        return fail(RORBK_ERR_UNSUPPORTED, "flexible AB-GMRES runs on FP64 storage");
+    hipStream_t s = h->stream;
+    const int64_t m = L.m, n = L.n, M1 = max_outer + 1;
+    h->rec_valid = 0;
+    h->profile = 0;
+    // workspaces of this call
+    double *V = nullptr, *Z = nullptr, *small = nullptr;
+    int rc = dalloc(&V, (size_t)(m * M1));
+    if (!rc) rc = dalloc(&Z, (size_t)(n * max_outer));
+    // hcol (M1), R (M1 * max_outer), cs, sn (max_outer), g (M1), est (2), beta (1)
+    const size_t nsmall = (size_t)(M1 + M1 * max_outer + 2 * max_outer + M1 + 3);
+    if (!rc) rc = dalloc(&small, nsmall);
+    if (!rc) rc = ensure_solve_buffers(h, inner_iters, false, 0, VEC_F64);
+    auto cleanup = [&]() {
+        dfree(V);
+        dfree(Z);
+        dfree(small);
+    };
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    double *hcol = small, *R = hcol + M1, *cs = R + M1 * max_outer, *sn = cs + max_outer;
+    double *g = sn + max_outer, *est = g + M1, *beta_d = est + 2;
+#define GCHK(expr)                                                                   \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            cleanup();                                                               \
+            return fail(RORBK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+        }                                                                            \
+    } while (0)
+    GCHK(launch_fill_zero(small, (int64_t)(sizeof(double) * nsmall), s));
+    GCHK(launch_fill_zero(Z, (int64_t)(sizeof(double) * n * max_outer), s));
+    // ||b|| and r0 = b - A x0, v_1 = r0 / beta
+    GCHK(launch_norm2(b, VEC_F64, m, h->d_red, h->d_red + 1, s));
+    GCHK(hipMemsetAsync(h->d_ctrl, 0, sizeof(Ctrl), s));
+    GCHK(residual(h, h->A, RORBK_F64, h->aligned, VEC_F64, x, h->d_axp));
+    GCHK(launch_gmres_start(b, h->d_axp, L.nseg, m, V, g, beta_d, s));
+    double hb[2] = {0.0, 0.0};
+    GCHK(hipMemcpyAsync(&hb[0], h->d_red + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    GCHK(hipMemcpyAsync(&hb[1], beta_d, sizeof(double), hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    const double bnorm = std::sqrt(hb[0]);
+    int64_t kend = 0, inner_total = 0;
+    bool conv = false;
+    if (hb[1] > 0.0) {
+        for (int64_t k = 0; k < max_outer; ++k) {
+            double *vk = V + k * m, *zk = Z + k * n;
+            // z_k: ROR-BK on A z = v_k from zero, sampler counter from k * inner_iters
+            int prc = prepare_tau(h, seed, k * inner_iters, inner_iters, false);
+            if (prc) { cleanup(); return prc; }
+            GCHK(launch_norm2(vk, VEC_F64, m, h->d_red, h->d_red + 2, s));
+            GCHK(launch_init_ctrl(h->d_ctrl, eta, h->d_red + 2, s));
+            RunOpts o;
+            memset(&o, 0, sizeof(o));
+            o.vec = VEC_F64;
+            o.A = h->A;
+            o.dt = RORBK_F64;
+            o.aligned = h->aligned;
+            o.b = vk;
+            o.x = zk;
+            int64_t ran = 0;
+            bool stopped = false;
+            int irc = run_iterations(h, o, 0, inner_iters, &ran, &stopped);
+            if (irc) { cleanup(); return irc; }
+            inner_total += ran;
+            // w = A z_k, Gram-Schmidt, Givens
+            GCHK(hipMemsetAsync(h->d_ctrl, 0, sizeof(Ctrl), s));
+            GCHK(residual(h, h->A, RORBK_F64, h->aligned, VEC_F64, zk, h->d_axp));
+            GCHK(launch_gmres_step(V, m, (int)k, h->d_axp, L.nseg, hcol, (int)M1, R, cs, sn, g,
+                                   est, s));
+            double he[2];
+            GCHK(hipMemcpyAsync(he, est, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            GCHK(hipStreamSynchronize(s));
+            kend = k + 1;
+            if (he[0] < tol * bnorm) {
+                conv = true;
+                break;
+            }
+            if (he[1] == 0.0) break;
+        }
+        GCHK(launch_gmres_update(Z, n, R, g, (int)kend, (int)M1, x, s));
+    } else {
+        conv = true;
+    }
+    // the true relative residual of the result
+    GCHK(hipMemsetAsync(h->d_ctrl, 0, sizeof(Ctrl), s));
+    GCHK(launch_init_ctrl(h->d_ctrl, 0.0, h->d_red + 1, s));
+    GCHK(residual(h, h->A, RORBK_F64, h->aligned, VEC_F64, x, h->d_axp));
+    SelectArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.vec = VEC_F64;
+    sa.b = b;
+    sa.axp = h->d_axp;
+    sa.nseg = L.nseg;
+    sa.r = h->d_r64;
+    sa.skip_topk = 1;
+    GCHK(launch_select(h, sa, s));
+    GCHK(hipMemcpyAsync(h->h_ctrl, h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+#undef GCHK
+    cleanup();
+    if (info) {
+        memset(info, 0, sizeof(*info));
+        info->iters = inner_total;
+        info->n_refine = (int32_t)kend;
+        info->converged = conv ? 1 : 0;
+        const Ctrl &c = *h->h_ctrl;
+        info->rrn = c.bnorm2 > 0 ? std::sqrt(c.rnorm2 / c.bnorm2) : 0.0;
+    }
+    return RORBK_OK;
+}
+
 int ror_bk_initial_solution(rorbk_handle h, const void *b, void *x0, int32_t vec_f32,
                             double *coef_host) {
     if (!h || !b || !x0) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");

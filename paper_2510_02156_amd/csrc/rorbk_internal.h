@@ -218,6 +218,15 @@ hipError_t launch_set_refine_ctrl(Ctrl *c, double tol, double eta,
 hipError_t launch_init_ctrl(Ctrl *c, double tol, const double *bnorm2, hipStream_t s);
 hipError_t launch_set_thr(Ctrl *c, double thr, hipStream_t s);
 hipError_t launch_axpy_f64(const double *d, double *x, int64_t n, hipStream_t s);
+// flexible AB-GMRES (Algorithm 3): start vector, one outer step (MGS + Givens),
+// final update x += Z y
+hipError_t launch_gmres_start(const double *b, const double *axp, int nseg, int64_t m,
+                              double *v1, double *g, double *out, hipStream_t s);
+hipError_t launch_gmres_step(double *V, int64_t m, int k, const double *axp, int nseg,
+                             double *hcol, int M1, double *R, double *cs, double *sn, double *g,
+                             double *est, hipStream_t s);
+hipError_t launch_gmres_update(const double *Z, int64_t n, const double *R, const double *g,
+                               int kend, int M1, double *x, hipStream_t s);
 // initial solution (Algorithm 2): y = column sums of the k x n centroids
 hipError_t launch_colsum(const double *cen, int64_t k, int64_t n, double *y, hipStream_t s);
 // coefficient from b and the products A y (axp), then x = coefficient * y
