@@ -49,11 +49,15 @@ extern "C" {
                                     rank-deficient block)                     */
 #define RORBK_ERR_NONFINITE 5    /* NaN or Inf in the residual               */
 #define RORBK_ERR_NOT_RECORDED 6 /* backward without a recorded forward      */
-#define RORBK_ERR_UNSUPPORTED 7  /* valid but not implemented (block larger
-                                    than RORBK_MAX_BLOCK_ROWS + 1 rows)       */
+#define RORBK_ERR_UNSUPPORTED 7  /* valid but not implemented (a block larger
+                                    than the limits below)                    */
 
-/* Largest supported rows per block (blocks may carry one extra row). */
+/* Largest rows per block (blocks may carry one extra row): CSR storage takes
+ * blocks of up to RORBK_MAX_BLOCK_ROWS + 1 rows; dense storage also takes
+ * larger blocks, of up to RORBK_MAX_BIG_BLOCK_ROWS rows, through a path built
+ * for them (blocked factorisations and multi-workgroup block steps). */
 #define RORBK_MAX_BLOCK_ROWS 160
+#define RORBK_MAX_BIG_BLOCK_ROWS 2048
 
 /* ------------------------------------------------------------------ matrix */
 #define RORBK_DENSE 0

@@ -25,6 +25,7 @@ RORBK_ERR_NONFINITE = 5
 RORBK_ERR_NOT_RECORDED = 6
 RORBK_ERR_UNSUPPORTED = 7
 RORBK_MAX_BLOCK_ROWS = 160
+RORBK_MAX_BIG_BLOCK_ROWS = 2048
 RORBK_DENSE, RORBK_CSR = 0, 1
 RORBK_F64, RORBK_F32, RORBK_BF16 = 0, 1, 2
 RORBK_REFINE, RORBK_RECORD, RORBK_REPLAY, RORBK_CHECKPOINT = 1, 2, 4, 8

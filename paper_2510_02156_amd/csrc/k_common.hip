@@ -334,8 +334,8 @@ __device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *_
                              const int32_t *replay_I, int32_t *I_out, double *rI_out,
                              uint64_t *keys, int32_t *ids, double *s_cn) {
     __shared__ int s_stop;
-    __shared__ uint64_t fk[MAXB];
-    __shared__ int32_t fi[MAXB];
+    __shared__ uint64_t fk[MAXK];
+    __shared__ int32_t fi[MAXK];
     constexpr int NCN = SEL_MERGE / 4;
     for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
     if (do_topk) {
@@ -929,6 +929,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                              const double *rI, const double *Pin, double *y, hipStream_t s) {
     const Layout &L = h->L;
+    if (K > MAXB) return launch_big_chol_solve(h, Gpart, K, rI, Pin, y, s);
     if (K <= 64) {
         hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K, h->lambda,
                            rI, Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);

@@ -657,6 +657,7 @@ hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A, i
 hipError_t launch_block_inverses_from_grams(const rorbk_handle_s *h, const double *Gs, int64_t kp,
                                             int32_t *d_fail, hipStream_t s) {
     const Layout &L = h->L;
+    if (L.bmax > MAXB) return launch_big_block_inverses(h, Gs, kp, d_fail, s);
     if (L.bmax <= 64)
         hipLaunchKernelGGL(k_block_inverse64, dim3((unsigned)L.k), dim3(64), 0, s, Gs, kp, L.q,
                            L.rem, h->lambda, h->d_H, d_fail);

@@ -71,7 +71,24 @@ bool aligned16(const void *p, int64_t ld, size_t es) {
 // Column chunking of the block step, the greedy Gram and the selection.
 void plan_layout(Layout &L) {
     const int64_t n = L.n;
-    if (L.format == RORBK_DENSE) {
+    const bool big = L.format == RORBK_DENSE && L.bmax > RORBK_MAX_BLOCK_ROWS + 1;
+    if (big) {
+        // large blocks: one 128-column slab per update workgroup (row chunks
+        // add the rest of the parallelism); greedy Gram chunks sized so that
+        // tiles x chunks is about 4096 workgroups
+        L.wu = 128;
+        L.nch_u = (int32_t)((n + 127) / 128);
+        const int64_t nt = (L.K + 15) / 16, tiles = nt * (nt + 1) / 2;
+        int64_t nch = (4096 + tiles - 1) / tiles;
+        if (nch > 64) nch = 64;
+        if (nch > (n + 31) / 32) nch = (n + 31) / 32;
+        if (nch < 1) nch = 1;
+        int64_t wg = (n + nch - 1) / nch;
+        wg = ((wg + 31) / 32) * 32;
+        L.wg = wg;
+        L.nch_g = (int32_t)((n + wg - 1) / wg);
+        L.nseg = (int32_t)((n + 2047) / 2048);
+    } else if (L.format == RORBK_DENSE) {
         const int64_t slabs = (n + 127) / 128;
         int64_t per = (slabs + 63) / 64;  // slabs per workgroup (<= 8 keeps x in LDS)
         if (per > 8) per = 8;
@@ -139,6 +156,17 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_ysum);
     dfree(h->d_ysum32);
     dfree(h->d_alg2);
+    dfree(h->d_bigG);
+    dfree(h->d_bigW);
+    dfree(h->d_bigr);
+    dfree(h->d_bigy);
+    {
+        char *p1 = (char *)h->d_xold, *p2 = (char *)h->d_dxp;
+        dfree(p1);
+        dfree(p2);
+        h->d_xold = nullptr;
+        h->d_dxp = nullptr;
+    }
     dfree(h->d_rhs32);
     dfree(h->d_d32);
     dfree(h->d_r64);
@@ -155,6 +183,7 @@ void destroy_all(rorbk_handle_s *h) {
 // ----------------------------------------------------------- dispatch ----
 
 hipError_t step(const rorbk_handle_s *h, const StepArgs &a) {
+    if (h->big) return launch_step_big(h, a, h->stream);
     if (h->L.format == RORBK_CSR) return launch_step_csr(h, a, h->stream);
     return launch_step_dense(h, a, h->stream);
 }
@@ -441,9 +470,15 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     L.K = L.q;
     L.bmax = L.q + (L.rem > 0 ? 1 : 0);
     if (L.bmax > RORBK_MAX_BLOCK_ROWS + 1) {
-        delete h;
-        return fail(RORBK_ERR_UNSUPPORTED, "blocks of %lld rows exceed the supported %d",
-                    (long long)L.bmax, RORBK_MAX_BLOCK_ROWS + 1);
+        const int lim = (L.format == RORBK_DENSE) ? RORBK_MAX_BIG_BLOCK_ROWS
+                                                  : RORBK_MAX_BLOCK_ROWS + 1;
+        if (L.bmax > lim) {
+            delete h;
+            return fail(RORBK_ERR_UNSUPPORTED, "blocks of %lld rows exceed the supported %d%s",
+                        (long long)L.bmax, lim,
+                        L.format == RORBK_DENSE ? "" : " for CSR storage");
+        }
+        h->big = 1;
     }
     plan_layout(L);
     h->stream = (hipStream_t)stream;
@@ -509,6 +544,20 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_selcnt, 1);
     ALLOC(h->d_ysum, L.n);
     ALLOC(h->d_alg2, 3);
+    if (h->big) {
+        const int64_t P = (K + 31) / 32;
+        ALLOC(h->d_bigG, (P + 1) * 32 * P * 32);
+        ALLOC(h->d_bigW, P * 32 * 32);
+        ALLOC(h->d_bigr, bmax);
+        ALLOC(h->d_bigy, bmax);
+        char *p1 = nullptr, *p2 = nullptr;
+        rc = dalloc(&p1, (size_t)(8 * L.n));
+        if (rc) { destroy_all(h); delete h; return rc; }
+        h->d_xold = p1;
+        rc = dalloc(&p2, (size_t)(8 * L.n * ((bmax + 63) / 64)));
+        if (rc) { destroy_all(h); delete h; return rc; }
+        h->d_dxp = p2;
+    }
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_ctrl, 3 * sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) {

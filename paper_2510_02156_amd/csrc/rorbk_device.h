@@ -15,6 +15,8 @@ namespace rorbk {
 constexpr int WAVE = 64;
 constexpr int MAXB = RORBK_MAX_BLOCK_ROWS + 1;          // largest block (rows)
 constexpr int PACKED_MAX = MAXB * (MAXB + 1) / 2;       // packed lower size
+constexpr int BIGB = RORBK_MAX_BIG_BLOCK_ROWS;          // largest block, dense large-block path
+constexpr int MAXK = BIGB > MAXB ? BIGB : MAXB;         // largest greedy set
 
 typedef uint16_t bf16_t;
 typedef double dvec2 __attribute__((ext_vector_type(2)));

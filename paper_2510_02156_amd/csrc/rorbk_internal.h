@@ -80,6 +80,14 @@ struct rorbk_handle_s {
     double *d_ysum;           // sum of the rows of A (n), for the initial solution
     float *d_ysum32;          // the same in FP32 (allocated on first use)
     double *d_alg2;           // <b, A y>, ||A y||^2, coefficient
+    // large-block path (dense blocks of more than RORBK_MAX_BLOCK_ROWS + 1 rows)
+    int32_t big;              // 1 when the large-block kernels run the steps
+    double *d_bigG;           // greedy system, padded, with the right-hand-side row
+    double *d_bigW;           // inverses of its diagonal tiles
+    double *d_bigr;           // r_S of a fixed block step (bmax)
+    double *d_bigy;           // y of a fixed block step (bmax)
+    void *d_xold;             // x before the step's update (vector type, n)
+    void *d_dxp;              // update column partials [row chunk][n] (vector type)
     double *d_P[2];           // partial A_S x per update chunk [nch][bmax]
     double *d_axp;            // residual partial products [nseg][m]
     void *d_r;                // residual (vector type)
@@ -232,6 +240,13 @@ hipError_t launch_colsum(const double *cen, int64_t k, int64_t n, double *y, hip
 // coefficient from b and the products A y (axp), then x = coefficient * y
 hipError_t launch_alg2(const void *b, int vec, const double *axp, int nseg, int64_t m,
                        const double *y, double *coef, void *x, int64_t n, hipStream_t s);
+
+// large-block path (dense): block step, greedy solve, stored inverses
+hipError_t launch_step_big(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
+hipError_t launch_big_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
+                                 const double *rI, const double *Pin, double *y, hipStream_t s);
+hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, int64_t kp,
+                                     int32_t *d_fail, hipStream_t s);
 
 // format-specific block step, residual products and greedy Gram
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);

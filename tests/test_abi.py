@@ -82,6 +82,27 @@ def test_struct_layouts_match_header():
     assert binding.rorbk_info.t_solve_s.offset == 24
 
 
+def test_block_size_limits_refused_before_any_device_call():
+    """Blocks above the supported sizes (2048 rows dense, 161 rows CSR) are
+    refused with RORBK_ERR_UNSUPPORTED by the argument checks, which run
+    before the library touches a device (the pointers are never read)."""
+    from paper_2510_02156_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("librorbk.so not built")
+    L = binding.lib()
+    fake = C.c_void_p(0x1000)
+    h = C.c_void_p()
+    for fmt, m, br in [(binding.RORBK_DENSE, 2 * 2049, 2049),
+                       (binding.RORBK_CSR, 2 * 162, 162)]:
+        A = binding.rorbk_matrix(format=fmt, dtype=binding.RORBK_F64, m=m, n=m, ld=m,
+                                 values=fake, rowptr=fake, colidx=fake, nnz=m,
+                                 values_f64=None)
+        rc = L.ror_bk_setup(C.byref(A), C.c_int64(br), C.c_double(1e-3), None, C.byref(h))
+        assert rc == binding.RORBK_ERR_UNSUPPORTED
+        assert not h.value
+        assert b"exceed" in L.ror_bk_last_error_message()
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2510_02156_amd import binding
     monkeypatch.setattr(binding, "_lib", None)

@@ -1,0 +1,216 @@
+"""GPU parity of the large-block path (dense blocks of more than 161 rows, up
+to 2048) against the FP64 oracle: the paper's own regime, 100 blocks of
+hundreds of rows (Section 3.1).
+
+Cases span several 32-row factorisation tiles with ragged tails (blocks of
+171/172, 402/403 and 300 rows), tall and wide shapes, and the largest block
+(2048 rows).  Bars as for the small-block path: partition, draws and greedy
+sets bit-exact; stored inverses within 50 cond(G) eps; FP64 iterates within
+1e-10 relative; FP32/BF16 storage within 1e-4 of the oracle run on the same
+rounded values with its selections replayed.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import dense_random_system, dense_svd_system
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2510_02156_amd as P  # noqa: E402
+from tests.gpu_util import bf16_tensor, bf16_values, dev, host, rel  # noqa: E402
+
+# m, n, block rows, lambda, generator
+CASES = [
+    (1200, 700, 170, 1.7e-4, "svd"),      # 7 blocks of 172/171 rows: 6 tiles, ragged
+    (2011, 900, 400, 4e-4, "randn"),      # 5 blocks of 403/402 rows: 13 tiles
+    (1500, 2200, 300, 3e-4, "unif1"),     # wide, 5 blocks of 300 rows
+]
+
+
+def system(m, n, kind, cfg=21):
+    if kind == "svd":
+        return dense_svd_system(m, n, 1e3, cfg=cfg + m)
+    return dense_random_system(m, n, cfg + m, kind)
+
+
+@pytest.mark.parametrize("m,n,br,lam,kind", CASES)
+def test_big_setup_matches_oracle(m, n, br, lam, kind):
+    s = system(m, n, kind)
+    print(f"big setup m={m} n={n} br={br}", flush=True)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    got = sol.setup_arrays()
+    off = O.partition(m, br)
+    np.testing.assert_array_equal(got["offsets"], off)
+    S = O.cosine_rowsums(s["A"], br)
+    np.testing.assert_allclose(got["S"], S, rtol=1e-12)
+    for t in sorted({0, sol.k // 2, sol.k - 1}):
+        rows = np.arange(off[t], off[t + 1])
+        L = O.block_factor(s["A"], rows, lam)
+        G = L @ L.T
+        Hg = sol.block_inverse(t)
+        assert Hg.shape == (len(rows), len(rows))
+        np.testing.assert_array_equal(Hg, Hg.T)          # stored exactly symmetric
+        e = rel(Hg, np.linalg.inv(G))
+        print(f"  block {t} ({len(rows)} rows): inverse rel err {e:.2e}", flush=True)
+        assert e < 50 * np.linalg.cond(G) * np.finfo(float).eps
+
+
+@pytest.mark.parametrize("m,n,br,lam,kind", CASES)
+def test_big_free_running_fp64(m, n, br, lam, kind):
+    s = system(m, n, kind)
+    iters = 8
+    ref = O.solve(s["A"], br, lam, s["b"], seed=5, max_iters=iters)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, info = sol.solve(dev(s["b"]), seed=5, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"big m={m} n={n} br={br}: {iters} iterations rel err {e:.2e}", flush=True)
+    assert info["iters"] == iters
+    assert e < 1e-10
+    np.testing.assert_allclose(rec["rrn"], ref["rrn_hist"], rtol=1e-9)
+
+
+def test_big_replay_fp64_with_x0():
+    m, n, br, lam = 1300, 800, 200, 2e-4
+    s = system(m, n, "randn", cfg=3)
+    x0 = np.random.default_rng(1).standard_normal(n)
+    iters = 12
+    ref = O.solve(s["A"], br, lam, s["b"], x0=x0, seed=7, max_iters=iters)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    sol.set_replay(ref["tau"], ref["I"], iters)
+    x, _ = sol.solve(dev(s["b"]), dev(x0), seed=0, tol=0.0, max_iters=iters, replay=True)
+    e = rel(host(x), ref["x"])
+    print(f"big replay with x0: rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_big_low_precision_replay(storage):
+    m, n, br, lam = 1400, 1000, 280, 2.8e-4
+    s = system(m, n, "svd", cfg=5)
+    if storage == "f32":
+        Av = s["A"].astype(np.float32).astype(np.float64)
+        At = dev(s["A"], torch.float32)
+    else:
+        Av = bf16_values(s["A"])
+        At = bf16_tensor(s["A"])
+    b = Av @ s["xstar"]
+    iters = 15
+    ref = O.solve(Av, br, lam, b, seed=4, max_iters=iters)
+    sol = P.Solver(At, br, lam)
+    sol.set_replay(ref["tau"], ref["I"], iters)
+    x, _ = sol.solve(dev(b, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
+    e = rel(host(x), ref["x"])
+    print(f"big {storage}: rel err vs FP64 oracle {e:.2e}", flush=True)
+    assert x.dtype == torch.float32
+    assert e < 1e-4
+
+
+def test_big_stop_test_and_resume():
+    m, n, br = 2400, 500, 240
+    s = system(m, n, "randn", cfg=9)
+    lam = 1e-6 * br
+    ref = O.solve(s["A"], br, lam, s["b"], seed=4, tol=1e-6, max_iters=300)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, info = sol.solve(dev(s["b"]), seed=4, tol=1e-6, max_iters=300)
+    print(f"big stop test: oracle {ref['iters']} iterations (converged {ref['converged']}), "
+          f"GPU {info['iters']}, rrn {info['rrn']:.2e}", flush=True)
+    assert ref["converged"]
+    assert info["iters"] == ref["iters"] and info["converged"] == ref["converged"]
+    assert rel(host(x), ref["x"]) < 1e-10
+    b = dev(s["b"])
+    x1, _ = sol.solve(b, seed=8, tol=0.0, max_iters=9)
+    x2, _ = sol.solve(b, seed=8, tol=0.0, max_iters=4)
+    x2, _ = sol.solve(b, x2, seed=8, tol=0.0, max_iters=5, start_iter=4)
+    assert torch.equal(x1, x2)
+
+
+def test_big_backward_matches_oracle():
+    m, n, br, lam = 1100, 600, 180, 1e-3
+    s = system(m, n, "svd", cfg=13)
+    rng = np.random.default_rng(2)
+    x0, xt = rng.standard_normal(n), rng.standard_normal(n)
+    iters = 6
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, _ = sol.solve(dev(s["b"]), dev(x0), seed=9, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    g = 2 * (host(x) - xt)
+    gb, gx0 = sol.backward(dev(g))
+    rb, rx0 = O.backward(s["A"], br, lam, rec["tau"], rec["I"], iters, False, g)
+    eb, ex = rel(host(gb), rb), rel(host(gx0), rx0)
+    print(f"big adjoint: dL/db {eb:.2e}, dL/dx0 {ex:.2e}", flush=True)
+    assert eb < 1e-10 and ex < 1e-10
+    # checkpointed recomputation gives the same gradients bit for bit
+    x2, _ = sol.solve(dev(s["b"]), dev(x0), seed=9, tol=0.0, max_iters=iters, checkpoint_every=4)
+    assert torch.equal(x, x2)
+    gb2, gx2 = sol.backward(dev(g))
+    assert torch.equal(gb, gb2) and torch.equal(gx0, gx2)
+
+
+def test_big_refine_fp32():
+    m, n, br = 3000, 600, 300
+    s = system(m, n, "randn", cfg=17)
+    lam = 1e-6 * br
+    A64 = dev(s["A"])
+    sol = P.Solver(A64.float(), br, lam, A64=A64)
+    x, info = sol.solve(dev(s["b"]), seed=2, tol=1e-9, max_iters=400, refine=True)
+    r = s["b"] - s["A"] @ host(x)
+    rrn = np.linalg.norm(r) / np.linalg.norm(s["b"])
+    print(f"big refine fp32: iters {info['iters']} outer {info['n_refine']} reported rrn "
+          f"{info['rrn']:.2e} FP64 rrn {rrn:.2e}", flush=True)
+    assert x.dtype == torch.float64
+    assert info["converged"] and rrn < 1e-9 * (1 + 1e-6)
+
+
+def test_big_fabgmres_matches_oracle():
+    m, n, br, lam = 1200, 500, 200, 2e-4
+    s = system(m, n, "svd", cfg=23)
+    kw = dict(seed=3, tol=1e-10, max_outer=6, inner_iters=3, eta=1e-2)
+    ref = O.fabgmres(s["A"], br, lam, s["b"], **kw)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, info = sol.fabgmres(dev(s["b"]), **kw)
+    e = rel(host(x), ref["x"])
+    print(f"big fabgmres: outer {info['outer']} (oracle {ref['outer']}), rel err {e:.2e}",
+          flush=True)
+    assert info["outer"] == ref["outer"]
+    assert e < 1e-9
+
+
+@pytest.mark.timeout(300)
+def test_big_largest_block():
+    """Blocks of 2048 rows, the largest the path takes: 64 factorisation tiles,
+    the whole greedy set in one system."""
+    m, n, br = 4096, 2100, 2048
+    s = system(m, n, "randn", cfg=29)
+    lam = 1e-6 * br
+    print("largest block: setup", flush=True)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    assert sol.k == 2
+    rows = np.arange(0, 2048)
+    L = O.block_factor(s["A"], rows, lam)
+    G = L @ L.T
+    assert rel(sol.block_inverse(0), np.linalg.inv(G)) < 50 * np.linalg.cond(G) * 2.2e-16
+    iters = 1
+    print("largest block: oracle", flush=True)
+    ref = O.solve(s["A"], br, lam, s["b"], seed=1, max_iters=iters)
+    x, _ = sol.solve(dev(s["b"]), seed=1, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"largest block: rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+
+
+def test_big_limits():
+    """2049-row dense blocks and 162-row CSR blocks are refused."""
+    A = dev(np.random.default_rng(0).standard_normal((2 * 2049, 8)))
+    with pytest.raises(P.RorBkError) as ei:
+        P.Solver(A, 2049, 1e-3)
+    assert ei.value.code == P.RORBK_ERR_UNSUPPORTED

@@ -8,6 +8,7 @@ from .gen import (  # noqa: F401
     haar,
     log_spaced,
     dense_svd_system,
+    dense_random_system,
     csr_system,
     make,
     to_bf16_bits,

@@ -3,7 +3,8 @@
 Every array is drawn on the host in FP64 from ``numpy.random.default_rng([cfg,
 stream])`` with fixed stream ids, so the oracle and the GPU library are fed the
 identical bytes.  Stream ids: 0 = U, 1 = V, 2 = x_star, 3 = sparse columns,
-4 = sparse values, 5 = row scales, 6 = x_t (differentiation target).
+4 = sparse values, 5 = row scales, 6 = x_t (differentiation target), 7 = the
+entries of the i.i.d. random dense matrices.
 
 The paper measures on SuiteSparse matrices, AIR Tools II tomography and dense
 random matrices (Section 3); none of those data are available here, so these
@@ -16,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 # Stream ids (second word of the numpy seed sequence).
-S_U, S_V, S_XSTAR, S_COLS, S_VALS, S_SCALE, S_XT = range(7)
+S_U, S_V, S_XSTAR, S_COLS, S_VALS, S_SCALE, S_XT, S_A = range(8)
 
 
 def haar(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
@@ -63,6 +64,29 @@ def dense_svd_system(m: int, n: int, cond: float, cfg: int,
     b = a @ xstar
     return {"format": "dense", "A": a, "b": b, "xstar": xstar, "m": m, "n": n,
             "s": s}
+
+
+def dense_random_system(m: int, n: int, cfg: int, dist: str = "randn") -> dict:
+    """Dense m x n matrix of i.i.d. entries, the random matrices of the
+    paper's dense experiments (Tables 3 and 5): ``randn`` draws N(0, 1),
+    ``unif1`` draws 1 + U(0, 1).  Planted x_star ~ N(0, 1), consistent
+    b = A x_star.  Drawn in row panels so the FP64 matrix is the only large
+    allocation.
+    """
+    ra = np.random.default_rng([cfg, S_A])
+    a = np.empty((m, n))
+    step = max(1, (1 << 24) // n)
+    for r0 in range(0, m, step):
+        r1 = min(m, r0 + step)
+        if dist == "randn":
+            a[r0:r1] = ra.standard_normal((r1 - r0, n))
+        elif dist == "unif1":
+            a[r0:r1] = 1.0 + ra.uniform(0.0, 1.0, (r1 - r0, n))
+        else:
+            raise ValueError(dist)
+    xstar = np.random.default_rng([cfg, S_XSTAR]).standard_normal(n)
+    b = a @ xstar
+    return {"format": "dense", "A": a, "b": b, "xstar": xstar, "m": m, "n": n}
 
 
 def csr_system(m: int, nnz_off: int, cfg: int, scale_lo: float = -6.0) -> dict:
@@ -129,6 +153,13 @@ WORKLOADS = {
     "diff_20000x1000": dict(cfg=5, kind="dense", m=20000, n=1000, cond=1e5,
                             f32=True, block_rows=50, lam=None, tol=0.0,
                             max_iters=300, checkpoint_every=20),
+    # the paper's own protocol (Section 3.1): 100 blocks, lambda = 1e-6 * rows
+    # per block, stop at RRN < 1e-6; shapes of Table 3 (randn) and Table 5
+    # (1 + U(0,1))
+    "randn_60000x10000": dict(cfg=6, kind="randn", m=60000, n=10000,
+                              block_rows=600, lam=None, tol=1e-6, max_iters=2000),
+    "unif_100000x10000": dict(cfg=7, kind="unif1", m=100000, n=10000,
+                              block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
 }
 
 
@@ -139,6 +170,8 @@ def make(name: str, m: int | None = None, n: int | None = None) -> dict:
     if w["kind"] == "csr":
         mm = m or w["m"]
         sysd = csr_system(mm, w["nnz_off"], cfg)
+    elif w["kind"] in ("randn", "unif1"):
+        sysd = dense_random_system(m or w["m"], n or w["n"], cfg, w["kind"])
     else:
         mm, nn = m or w["m"], n or w["n"]
         sysd = dense_svd_system(mm, nn, w["cond"], cfg,
