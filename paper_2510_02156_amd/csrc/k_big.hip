@@ -6,11 +6,12 @@
 //  - the symmetric positive definite systems (each fixed block's Gram at setup,
 //    the greedy block's Gram every iteration) are factored by a right-looking
 //    blocked Cholesky on 32 x 32 tiles in global memory, batched over
-//    matrices, three launches per tile column: the diagonal tile is factored on
-//    one wave and inverted, the tiles below it are multiplied by that inverse,
-//    and the trailing tiles are updated.  Matrices are padded to whole tiles
-//    with the identity.  The greedy system carries its right-hand side as an
-//    extra tile row, so the factorisation also performs the forward solve;
+//    matrices, one launch per tile column: every workgroup scales the two
+//    panel tiles it needs by the inverse of the diagonal tile and updates one
+//    trailing tile (FP64 MFMA), and the workgroup of the next diagonal tile
+//    factors and inverts it at once.  Matrices are padded to whole tiles with
+//    the identity.  The greedy system carries its right-hand side as an extra
+//    tile row, so the factorisation also performs the forward solve;
 //  - the setup then forms L^{-1} by tile rows and the stored inverse
 //    H_t = L^{-T} L^{-1}, exactly symmetric;
 //  - a fixed block step is four kernels: r_S from the partial products, y =
@@ -79,63 +80,237 @@ __global__ __launch_bounds__(256) void k_big_unpack(const double *__restrict__ s
     G[(int64_t)bt * rows * ld + e] = v;
 }
 
-// Diagonal tile p of every matrix: Cholesky on one wave (lane i & 31 holds row
-// i), written back in place, and its inverse (column j by lane j) into
-// W[bt * P + p] (32 x 32 row-major).  A pivot that is not positive sets *fail
-// (setup) or the control block's NOT_SPD status (greedy solve).
-__global__ __launch_bounds__(64) void k_big_potrf(double *__restrict__ G, int ld, int64_t mstride,
-                                                  int p, int P, double *__restrict__ W,
-                                                  int32_t *__restrict__ fail,
-                                                  Ctrl *__restrict__ ctrl) {
-    if (ctrl_done(ctrl)) return;
-    __shared__ double Ls[TB][TB + 1];
-    const int bt = blockIdx.x, lane = threadIdx.x, i = lane & (TB - 1);
-    double *T = G + (int64_t)bt * mstride + (int64_t)(p * TB) * ld + p * TB;
-    double a[TB];
+// Orders one wave's LDS accesses across lanes (a compiler barrier for memory
+// operations; LDS instructions of one wave execute in order).
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 1 / sqrt(d): the hardware estimate refined by two steps of Newton's
+// iteration for the reciprocal square root, r <- r (3 - d r^2) / 2.
+__device__ __forceinline__ double rsq_nr(double d) {
+    double r = __builtin_amdgcn_rsq(d);
 #pragma unroll
-    for (int j = 0; j < TB; ++j) a[j] = (j <= i) ? T[(int64_t)i * ld + j] : 0.0;
+    for (int it = 0; it < 2; ++it) {
+        const double h = d * r;
+        const double e = __builtin_fma(-h, r, 1.0);
+        r = __builtin_fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
+// 16 x 16 MFMA product on one wave from LDS (row strides RA, RB):
+// acc += A B^T (TRANSB) or A B.  Result element (i, j) sits in register i / 4
+// of lane (i % 4) * 16 + j; k is summed in steps of 4, in order.
+template <bool TRANSB>
+__device__ __forceinline__ dvec4 mm16(const double *A, int RA, const double *B, int RB, dvec4 acc) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double a = A[li * RA + k0 + lk];
+        const double b = TRANSB ? B[li * RB + k0 + lk] : B[(k0 + lk) * RB + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void st16(double *D, int RD, dvec4 v, double scale) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) D[(lk + 4 * r) * RD + li] = scale * v[r];
+}
+
+// Cholesky factor and inverse of a 16 x 16 SPD block in LDS (row stride RS) on
+// one wave, lane i & 15 holding row i: right-looking elimination with the
+// columns broadcast by readlane; the block is overwritten by L (zeros above
+// the diagonal) and Wl receives L^{-1}, column j by lane j (forward
+// substitution, the earlier columns applied as they are found).
+__device__ __forceinline__ void f16(double *S, int RS, double *Wl, bool &ok) {
+    const int lane = threadIdx.x & 63, i = lane & 15;
+    double a[16], rk[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a[j] = (j <= i) ? S[i * RS + j] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const double d = bcast64(a[k], k);
+        ok = ok && (d > 0.0) && isfinite(d);
+        const double r = rsq_nr(d);
+        rk[k] = r;
+        a[k] = (i == k) ? d * r : a[k] * r;
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) a[j] = __builtin_fma(-a[k], bcast64(a[k], j), a[j]);
+    }
+    wsync();
+    if (lane < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) S[i * RS + j] = (j <= i) ? a[j] : 0.0;
+    }
+    wsync();
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        const double w = acc[c] * rk[c];
+        acc[c] = w;
+#pragma unroll
+        for (int r = c + 1; r < 16; ++r) acc[r] = __builtin_fma(-S[r * RS + c], w, acc[r]);
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Wl[r * RS + i] = acc[r];
+    }
+    wsync();
+}
+
+// Cholesky factor L and inverse W = L^{-1} of a 32 x 32 SPD tile in LDS (lower
+// part read; overwritten by L with zeros above), in two levels of 16:
+// L11, W11; L21 = A21 W11^T; A22 -= L21 L21^T; L22, W22; W21 = -W22 L21 W11.
+// Runs on wave 0; ends with a workgroup barrier.  Returns false (to wave 0) if
+// a pivot is not positive.
+__device__ bool tile_factor32(double (*S)[TB + 1], double (*Wl)[TB + 1]) {
     bool ok = true;
+    if (threadIdx.x < 64) {
+        constexpr int RS = TB + 1;
+        const dvec4 z4 = {0.0, 0.0, 0.0, 0.0};
+        f16(&S[0][0], RS, &Wl[0][0], ok);
+        const dvec4 l21 = mm16<true>(&S[16][0], RS, &Wl[0][0], RS, z4);
+        wsync();
+        st16(&S[16][0], RS, l21, 1.0);
+        wsync();
+        const dvec4 u = mm16<true>(&S[16][0], RS, &S[16][0], RS, z4);
+        {
+            const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
 #pragma unroll
-    for (int k = 0; k < TB; ++k) {
-        const double piv = bcast64(a[k], k);
-        ok = ok && (piv > 0.0) && isfinite(piv);
-        const double lkk = sqrt(piv), inv = 1.0 / lkk;
-        if (i > k) a[k] *= inv;
-        if (i == k) a[k] = lkk;
-#pragma unroll
-        for (int j = k + 1; j < TB; ++j) {
-            const double ljk = bcast64(a[k], j);
-            if (i >= j) a[j] = __builtin_fma(-a[k], ljk, a[j]);
+            for (int r = 0; r < 4; ++r) S[16 + lk + 4 * r][16 + li] -= u[r];
         }
-    }
-    if (lane < TB) {
-#pragma unroll
-        for (int j = 0; j < TB; ++j) {
-            if (j <= i) T[(int64_t)i * ld + j] = a[j];
-            Ls[i][j] = (j <= i) ? a[j] : 0.0;
+        wsync();
+        f16(&S[16][16], RS, &Wl[16][16], ok);
+        const dvec4 t1 = mm16<false>(&S[16][0], RS, &Wl[0][0], RS, z4);     // L21 W11
+        wsync();
+        st16(&Wl[16][0], RS, t1, 1.0);
+        wsync();
+        const dvec4 w21 = mm16<false>(&Wl[16][16], RS, &Wl[16][0], RS, z4);  // W22 (L21 W11)
+        wsync();
+        st16(&Wl[16][0], RS, w21, -1.0);
+        {
+            const int l = threadIdx.x & 63;
+            for (int e = l; e < 256; e += 64) {
+                S[e >> 4][16 + (e & 15)] = 0.0;
+                Wl[e >> 4][16 + (e & 15)] = 0.0;
+            }
         }
-    }
-    if (lane == 0 && !ok) {
-        if (fail) *fail = 1;
-        if (ctrl) {
-            ctrl->status = RORBK_ERR_NOT_SPD;
-            ctrl->done = 1;
-        }
+        wsync();
     }
     __syncthreads();
-    if (lane < TB) {
-        const int jc = lane;   // column jc of the tile's inverse
-        double w[TB];
+    return ok;
+}
+
+// 32 x 32 products on four waves from LDS: wave w computes the 16 x 16
+// sub-tile (w / 2, w % 2) of A B^T; k summed in order.
+__device__ __forceinline__ dvec4 mm32_abt(const double (*A)[TB + 1], const double (*B)[TB + 1]) {
+    const int w = threadIdx.x >> 6, R = w >> 1, C = w & 1;
+    const dvec4 z4 = {0.0, 0.0, 0.0, 0.0};
+    dvec4 acc = mm16<true>(&A[R * 16][0], TB + 1, &B[C * 16][0], TB + 1, z4);
+    return mm16<true>(&A[R * 16][16], TB + 1, &B[C * 16][16], TB + 1, acc);
+}
+
+__device__ __forceinline__ void st32(double (*D)[TB + 1], dvec4 v) {
+    const int w = threadIdx.x >> 6, R = w >> 1, C = w & 1;
+    st16(&D[R * 16][C * 16], TB + 1, v, 1.0);
+}
+
+__device__ __forceinline__ void tile_load(double (*S)[TB + 1], const double *src, int ld) {
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
+        S[e / TB][e % TB] = src[(int64_t)(e / TB) * ld + e % TB];
+}
+
+// transposed: S[c][r] = src[r][c]
+__device__ __forceinline__ void tile_load_t(double (*S)[TB + 1], const double *src, int ld) {
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
+        S[e % TB][e / TB] = src[(int64_t)(e / TB) * ld + e % TB];
+}
+
+__device__ __forceinline__ void tile_store(double *dst, int ld, const double (*S)[TB + 1]) {
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
+        dst[(int64_t)(e / TB) * ld + e % TB] = S[e / TB][e % TB];
+}
+
+// One tile column of the right-looking blocked Cholesky, all matrices of the
+// batch at once (grid x).  Launch p >= 0 covers the tiles (I, J) with
+// p < J <= I < PR (grid y, lower triangle by rows):
+//   L_Ip = G_Ip W_p^T and L_Jp = G_Jp W_p^T (each workgroup forms the two it
+//   needs; the (I, p + 1) workgroups store L_Ip in Lf),
+//   G_IJ -= L_Ip L_Jp^T,
+// and the workgroup of the new diagonal tile (p + 1, p + 1) factors it at once
+// into Lf and its inverse into W.  Launch p = -1 factors tile (0, 0).  In the
+// greedy form (PR = P + 1) tile row P is the right-hand side, whose last slot
+// (P, P) only completes L_{P, P-1}; G keeps the updated, unscaled tiles.
+__global__ __launch_bounds__(256) void k_big_chol_col(double *__restrict__ G,
+                                                      double *__restrict__ Lf, int ld,
+                                                      int64_t mstride, int p, int P,
+                                                      double *__restrict__ W,
+                                                      int32_t *__restrict__ fail,
+                                                      Ctrl *__restrict__ ctrl) {
+    if (ctrl_done(ctrl)) return;
+    __shared__ double sW[TB][TB + 1], sA[TB][TB + 1], sB[TB][TB + 1], sT[TB][TB + 1];
+    const int bt = blockIdx.x;
+    int I = 0, J = 0;
+    if (p >= 0) {
+        const int f = blockIdx.y;
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= f) ++a;
+        I = p + 1 + a;
+        J = p + 1 + (f - a * (a + 1) / 2);
+        if (J >= P && J != p + 1) return;   // unused right-hand-side slot
+    }
+    const bool rhs_slot = J >= P;
+    double *Gb = G + (int64_t)bt * mstride;
+    double *Lb = Lf + (int64_t)bt * mstride;
+    if (p >= 0) {
+        const double *Wp = W + ((int64_t)bt * P + p) * TB * TB;
+        for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) sW[e / TB][e % TB] = Wp[e];
+        tile_load(sA, Gb + (int64_t)(I * TB) * ld + p * TB, ld);
+        if (J != I) tile_load(sB, Gb + (int64_t)(J * TB) * ld + p * TB, ld);
+    }
+    if (!rhs_slot) tile_load(sT, Gb + (int64_t)(I * TB) * ld + J * TB, ld);
+    __syncthreads();
+    if (p >= 0) {
+        const dvec4 li = mm32_abt(sA, sW);
+        dvec4 lj = li;
+        if (J != I) lj = mm32_abt(sB, sW);
+        __syncthreads();
+        st32(sA, li);
+        if (J != I) st32(sB, lj);
+        __syncthreads();
+        if (J == p + 1) tile_store(Lb + (int64_t)(I * TB) * ld + p * TB, ld, sA);
+        if (rhs_slot) return;
+        const dvec4 u = mm32_abt(sA, (J != I) ? sB : sA);
+        {
+            const int w = threadIdx.x >> 6, R = w >> 1, C = w & 1;
+            const int l = threadIdx.x & 63, lci = l & 15, lk = l >> 4;
 #pragma unroll
-        for (int r = 0; r < TB; ++r) {
-            double s = (r == jc) ? 1.0 : 0.0;
-#pragma unroll
-            for (int c = 0; c < r; ++c) s = __builtin_fma(-Ls[r][c], w[c], s);
-            w[r] = (r >= jc) ? s / Ls[r][r] : 0.0;
+            for (int r = 0; r < 4; ++r) sT[R * 16 + lk + 4 * r][C * 16 + lci] -= u[r];
         }
-        double *Wb = W + ((int64_t)bt * P + p) * TB * TB;
-#pragma unroll
-        for (int r = 0; r < TB; ++r) Wb[r * TB + jc] = w[r];
+        __syncthreads();
+    }
+    if (I == J && (p < 0 || J == p + 1)) {
+        // the new diagonal tile: factor in place, inverse into sW
+        const bool ok = tile_factor32(sT, sW);
+        if (threadIdx.x == 0 && !ok) {
+            if (fail) *fail = 1;
+            if (ctrl) {
+                ctrl->status = RORBK_ERR_NOT_SPD;
+                ctrl->done = 1;
+            }
+        }
+        tile_store(Lb + (int64_t)(J * TB) * ld + J * TB, ld, sT);
+        double *Wj = W + ((int64_t)bt * P + J) * TB * TB;
+        for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) Wj[e] = sW[e / TB][e % TB];
+    } else {
+        tile_store(Gb + (int64_t)(I * TB) * ld + J * TB, ld, sT);
     }
 }
 
@@ -153,77 +328,15 @@ __device__ __forceinline__ void tile_abt(const double (*A)[TB + 1], const double
     }
 }
 
-__device__ __forceinline__ void tile_load(double (*S)[TB + 1], const double *src, int ld) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
-        S[e / TB][e % TB] = src[(int64_t)(e / TB) * ld + e % TB];
-}
-
-// transposed: S[c][r] = src[r][c]
-__device__ __forceinline__ void tile_load_t(double (*S)[TB + 1], const double *src, int ld) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
-        S[e % TB][e / TB] = src[(int64_t)(e / TB) * ld + e % TB];
-}
-
-// Tiles below the diagonal of tile column p (tile rows p+1 .. PR-1):
-// L_Ip = G_Ip W_p^T.
-__global__ __launch_bounds__(256) void k_big_trsm(double *__restrict__ G, int ld, int64_t mstride,
-                                                  int p, int P, const double *__restrict__ W,
-                                                  const Ctrl *__restrict__ ctrl) {
-    if (ctrl_done(ctrl)) return;
-    __shared__ double sA[TB][TB + 1], sW[TB][TB + 1];
-    const int bt = blockIdx.x, I = p + 1 + blockIdx.y;
-    double *T = G + (int64_t)bt * mstride + (int64_t)(I * TB) * ld + p * TB;
-    tile_load(sA, T, ld);
-    const double *Wb = W + ((int64_t)bt * P + p) * TB * TB;
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) sW[e / TB][e % TB] = Wb[e];
-    __syncthreads();
-    double out[4];
-    tile_abt(sA, sW, out);
-    const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) T[(int64_t)r * ld + c0 + u] = out[u];
-}
-
-// Trailing tiles (I, J), p < J <= I, J < P, I < PR: G_IJ -= L_Ip L_Jp^T.
-// Flat index f: first the triangle of tile rows p+1 .. P-1, then (PR > P) the
-// right-hand-side tile row P, columns p+1 .. P-1.
-__global__ __launch_bounds__(256) void k_big_syrk(double *__restrict__ G, int ld, int64_t mstride,
-                                                  int p, int P, const Ctrl *__restrict__ ctrl) {
-    if (ctrl_done(ctrl)) return;
-    __shared__ double sA[TB][TB + 1], sB[TB][TB + 1];
-    const int bt = blockIdx.x, f = blockIdx.y;
-    const int nr = P - p - 1, tri = nr * (nr + 1) / 2;
-    int I, J;
-    if (f < tri) {
-        int a = 0;
-        while ((a + 1) * (a + 2) / 2 <= f) ++a;
-        I = p + 1 + a;
-        J = p + 1 + (f - a * (a + 1) / 2);
-    } else {
-        I = P;
-        J = p + 1 + (f - tri);
-    }
-    double *Gb = G + (int64_t)bt * mstride;
-    tile_load(sA, Gb + (int64_t)(I * TB) * ld + p * TB, ld);
-    tile_load(sB, Gb + (int64_t)(J * TB) * ld + p * TB, ld);
-    __syncthreads();
-    double out[4];
-    tile_abt(sA, sB, out);
-    double *T = Gb + (int64_t)(I * TB) * ld + J * TB;
-    const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) T[(int64_t)r * ld + c0 + u] -= out[u];
-}
-
-// Row of tiles I of X = L^{-1}: X_II = W_I and, for J < I,
+// Row of tiles I of X = L^{-1} (L from Lf): X_II = W_I and, for J < I,
 // X_IJ = -W_I sum_{k=J}^{I-1} L_Ik X_kJ (sum in k order).
-__global__ __launch_bounds__(256) void k_big_invrow(const double *__restrict__ G, int ld, int I,
+__global__ __launch_bounds__(256) void k_big_invrow(const double *__restrict__ Lf, int ld, int I,
                                                     const double *__restrict__ W, int P,
                                                     double *__restrict__ X) {
     __shared__ double sA[TB][TB + 1], sB[TB][TB + 1];
     const int bt = blockIdx.x, J = blockIdx.y;
     const int64_t ms = (int64_t)ld * ld;
-    const double *Gb = G + (int64_t)bt * ms;
+    const double *Lb = Lf + (int64_t)bt * ms;
     double *Xb = X + (int64_t)bt * ms;
     const double *WI = W + ((int64_t)bt * P + I) * TB * TB;
     const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
@@ -235,7 +348,7 @@ __global__ __launch_bounds__(256) void k_big_invrow(const double *__restrict__ G
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = J; k < I; ++k) {
-        tile_load(sA, Gb + (int64_t)(I * TB) * ld + k * TB, ld);     // L_Ik
+        tile_load(sA, Lb + (int64_t)(I * TB) * ld + k * TB, ld);     // L_Ik
         tile_load_t(sB, Xb + (int64_t)(k * TB) * ld + J * TB, ld);   // X_kJ^T
         __syncthreads();
         double out[4];
@@ -293,40 +406,44 @@ __global__ __launch_bounds__(256) void k_big_xtx(const double *__restrict__ X, i
 }
 
 // Backward solve L^T y = z of the greedy system (one workgroup), z being the
-// right-hand-side row left by the factorisation.  For each tile column p from
-// the last: t = z_p - sum_{k > p} L_kp^T y_k (32 column sums over row segments,
-// segments added in order), then y_p = W_p^T t.
+// right-hand-side row of the factor.  For each tile column p from the last:
+// t = z_p - sum_{k > p} L_kp^T y_k (thread (r, s) sums the rows s, s + 32, ...
+// of column r; the 32 row segments are added in order), then y_p = W_p^T t.
+// Every load of a step (its column block of L, W_p) is issued together.
 constexpr int BS_T = 1024;
+constexpr int BS_R = 32;   // rows per thread per round
 
-__global__ __launch_bounds__(BS_T) void k_big_bsolve(const double *__restrict__ G, int ld, int P,
+__global__ __launch_bounds__(BS_T) void k_big_bsolve(const double *__restrict__ Lf, int ld, int P,
                                                      const double *__restrict__ W, int K,
                                                      double *__restrict__ y,
                                                      const Ctrl *__restrict__ ctrl) {
     if (ctrl_done(ctrl)) return;
     __shared__ double z[BIGB];
     __shared__ double part[TB][TB + 1];
+    __shared__ double sWp[TB][TB + 1];
     __shared__ double t[TB];
     const int tid = threadIdx.x, r = tid & (TB - 1), sg = tid >> 5;
-    for (int i = tid; i < P * TB; i += BS_T) z[i] = G[(int64_t)ld * ld + i];
+    for (int i = tid; i < P * TB; i += BS_T) z[i] = Lf[(int64_t)ld * ld + i];
     __syncthreads();
     for (int p = P - 1; p >= 0; --p) {
+        const double wv = W[(int64_t)p * TB * TB + tid];
         double s = 0.0;
-        const int c0 = (p + 1) * TB + sg;
-        constexpr int U = 8;
-        for (int cb = c0; cb < P * TB; cb += U * TB) {
-            double gv[U];
+        const int nr = P - p - 1;                 // tile rows below the diagonal
+        for (int u0 = 0; u0 < nr; u0 += BS_R) {
+            double gv[BS_R];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = cb + u * TB;
-                gv[u] = (c < P * TB) ? G[(int64_t)c * ld + p * TB + r] : 0.0;
+            for (int u = 0; u < BS_R; ++u) {
+                const int c = (p + 1 + u0 + u) * TB + sg;
+                gv[u] = (u0 + u < nr) ? Lf[(int64_t)c * ld + p * TB + r] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = cb + u * TB;
-                if (c < P * TB) s = __builtin_fma(gv[u], z[c], s);
+            for (int u = 0; u < BS_R; ++u) {
+                const int c = (p + 1 + u0 + u) * TB + sg;
+                if (u0 + u < nr) s = __builtin_fma(gv[u], z[c], s);
             }
         }
         part[r][sg] = s;
+        sWp[tid >> 5][tid & 31] = wv;
         __syncthreads();
         if (tid < TB) {
             double v = z[p * TB + tid];
@@ -335,9 +452,8 @@ __global__ __launch_bounds__(BS_T) void k_big_bsolve(const double *__restrict__ 
         }
         __syncthreads();
         if (tid < TB) {
-            const double *Wp = W + (int64_t)p * TB * TB;
             double v = 0.0;
-            for (int c = tid; c < TB; ++c) v = __builtin_fma(Wp[c * TB + tid], t[c], v);
+            for (int c = tid; c < TB; ++c) v = __builtin_fma(sWp[c][tid], t[c], v);
             z[p * TB + tid] = v;
         }
         __syncthreads();
@@ -584,28 +700,23 @@ __global__ __launch_bounds__(BIG_T) void k_big_apply(BigP p) {
 
 // ------------------------------------------------------------ launchers --
 // Factor `batch` padded matrices (rows x ld each, rows = ld or ld + TB) in
-// place, keeping every diagonal tile's inverse in W[bt * P + p].
-static hipError_t big_potrf(double *G, int ld, int rows, int batch, double *W, int32_t *fail,
-                            Ctrl *ctrl, hipStream_t s) {
+// G: L into Lf, every diagonal tile's inverse into W[bt * P + p].
+static hipError_t big_potrf(double *G, double *Lf, int ld, int rows, int batch, double *W,
+                            int32_t *fail, Ctrl *ctrl, hipStream_t s) {
     const int P = ld / TB, PR = rows / TB;
     const int64_t ms = (int64_t)rows * ld;
-    for (int p = 0; p < P; ++p) {
-        hipLaunchKernelGGL(k_big_potrf, dim3(batch), dim3(64), 0, s, G, ld, ms, p, P, W, fail,
-                           ctrl);
-        if (PR - p - 1 > 0)
-            hipLaunchKernelGGL(k_big_trsm, dim3(batch, PR - p - 1), dim3(256), 0, s, G, ld, ms, p,
-                               P, (const double *)W, (const Ctrl *)ctrl);
-        const int nr = P - p - 1;
-        const int nt = nr * (nr + 1) / 2 + (PR > P ? nr : 0);
-        if (nt > 0)
-            hipLaunchKernelGGL(k_big_syrk, dim3(batch, nt), dim3(256), 0, s, G, ld, ms, p, P,
-                               (const Ctrl *)ctrl);
+    const int last = (PR > P) ? P - 1 : P - 2;
+    for (int p = -1; p <= last; ++p) {
+        const int nt = (p < 0) ? 1 : (PR - p - 1) * (PR - p) / 2;
+        hipLaunchKernelGGL(k_big_chol_col, dim3(batch, nt), dim3(256), 0, s, G, Lf, ld, ms, p, P,
+                           W, fail, ctrl);
     }
     return hipGetLastError();
 }
 
 // Stored inverses of every fixed block from packed Grams Gs[t][kp], in
-// batches of blocks that keep the two padded work arrays near 1 GiB.
+// batches of blocks that keep the two padded work arrays near 1 GiB each
+// (the second holds L, then L^{-1} is formed in the first).
 hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, int64_t kp,
                                      int32_t *d_fail, hipStream_t s) {
     const Layout &L = h->L;
@@ -614,9 +725,9 @@ hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, 
     int64_t bmaxb = ((int64_t)1 << 27) / ms;   // 2^27 doubles = 1 GiB per array
     if (bmaxb < 1) bmaxb = 1;
     if (bmaxb > L.k) bmaxb = L.k;
-    double *G = nullptr, *X = nullptr, *W = nullptr;
+    double *G = nullptr, *Lf = nullptr, *W = nullptr;
     hipError_t e = hipMallocAsync((void **)&G, sizeof(double) * (size_t)(bmaxb * ms), s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&X, sizeof(double) * (size_t)(bmaxb * ms), s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&Lf, sizeof(double) * (size_t)(bmaxb * ms), s);
     if (e == hipSuccess)
         e = hipMallocAsync((void **)&W, sizeof(double) * (size_t)(bmaxb * P * TB * TB), s);
     for (int64_t t0 = 0; t0 < L.k && e == hipSuccess; t0 += bmaxb) {
@@ -625,23 +736,25 @@ hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, 
                            dim3(256), 0, s, Gs + t0 * kp, kp, (int64_t)0, 1, 0, t0, L.q, L.rem,
                            h->lambda, ld, ld, (const double *)nullptr, (const double *)nullptr, 0,
                            0, G, (const Ctrl *)nullptr);
-        e = big_potrf(G, ld, ld, batch, W, d_fail, nullptr, s);
+        e = big_potrf(G, Lf, ld, ld, batch, W, d_fail, nullptr, s);
         if (e != hipSuccess) break;
+        double *X = G;   // G is free once factored
         for (int I = 0; I < P; ++I)
             hipLaunchKernelGGL(k_big_invrow, dim3((unsigned)batch, I + 1), dim3(256), 0, s,
-                               (const double *)G, ld, I, (const double *)W, P, X);
+                               (const double *)Lf, ld, I, (const double *)W, P, X);
         hipLaunchKernelGGL(k_big_xtx, dim3((unsigned)batch, P * (P + 1) / 2), dim3(256), 0, s,
                            (const double *)X, ld, P, t0, L.q, L.rem, h->d_H);
         e = hipGetLastError();
     }
     if (G) (void)hipFreeAsync(G, s);
-    if (X) (void)hipFreeAsync(X, s);
+    if (Lf) (void)hipFreeAsync(Lf, s);
     if (W) (void)hipFreeAsync(W, s);
     return e;
 }
 
 // The greedy block's system (A_I A_I^T + lambda I) y = rhs from the Gram
-// partials: unpack with the right-hand-side row, factor, backward solve.
+// partials: unpack with the right-hand-side row, factor (which also solves
+// L z = rhs), backward solve.
 hipError_t launch_big_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                                  const double *rI, const double *Pin, double *y, hipStream_t s) {
     const Layout &L = h->L;
@@ -651,9 +764,9 @@ hipError_t launch_big_chol_solve(const rorbk_handle_s *h, const double *Gpart, i
                        Gpart, (int64_t)0, KP, (int)L.nch_g, K, (int64_t)0, L.q, L.rem, h->lambda,
                        ld, rows, rI, Pin, (int)L.nch_u, (int)L.bmax, h->d_bigG,
                        (const Ctrl *)h->d_ctrl);
-    hipError_t e = big_potrf(h->d_bigG, ld, rows, 1, h->d_bigW, nullptr, h->d_ctrl, s);
+    hipError_t e = big_potrf(h->d_bigG, h->d_bigL, ld, rows, 1, h->d_bigW, nullptr, h->d_ctrl, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_big_bsolve, dim3(1), dim3(BS_T), 0, s, (const double *)h->d_bigG, ld, P,
+    hipLaunchKernelGGL(k_big_bsolve, dim3(1), dim3(BS_T), 0, s, (const double *)h->d_bigL, ld, P,
                        (const double *)h->d_bigW, K, y, (const Ctrl *)h->d_ctrl);
     return hipGetLastError();
 }

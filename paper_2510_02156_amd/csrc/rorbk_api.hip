@@ -157,6 +157,7 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_ysum32);
     dfree(h->d_alg2);
     dfree(h->d_bigG);
+    dfree(h->d_bigL);
     dfree(h->d_bigW);
     dfree(h->d_bigr);
     dfree(h->d_bigy);
@@ -547,6 +548,7 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     if (h->big) {
         const int64_t P = (K + 31) / 32;
         ALLOC(h->d_bigG, (P + 1) * 32 * P * 32);
+        ALLOC(h->d_bigL, (P + 1) * 32 * P * 32);
         ALLOC(h->d_bigW, P * 32 * 32);
         ALLOC(h->d_bigr, bmax);
         ALLOC(h->d_bigy, bmax);

@@ -83,6 +83,7 @@ struct rorbk_handle_s {
     // large-block path (dense blocks of more than RORBK_MAX_BLOCK_ROWS + 1 rows)
     int32_t big;              // 1 when the large-block kernels run the steps
     double *d_bigG;           // greedy system, padded, with the right-hand-side row
+    double *d_bigL;           // its Cholesky factor (same layout)
     double *d_bigW;           // inverses of its diagonal tiles
     double *d_bigr;           // r_S of a fixed block step (bmax)
     double *d_bigy;           // y of a fixed block step (bmax)
