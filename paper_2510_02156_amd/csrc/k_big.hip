@@ -122,45 +122,110 @@ __device__ __forceinline__ void st16(double *D, int RD, dvec4 v, double scale) {
     for (int r = 0; r < 4; ++r) D[(lk + 4 * r) * RD + li] = scale * v[r];
 }
 
+// Broadcast of lane J of each 16-lane row to the whole row (DPP row_newbcast,
+// one 64-bit move, the value stays in vector registers).
+template <int J>
+__device__ __forceinline__ double rowbc(double v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xf, 0xf, false);
+}
+
+// Pieces of one elimination step of f16 (compile-time indices, so every
+// register index is static): the trailing update of row i of the block and
+// the update of row i of the running transformation.
+// acc += (src of lane J of the 16-lane row) * mul.
+template <int J>
+__device__ __forceinline__ void fmac_bc(double &acc, double src, double mul) {
+    acc = __builtin_fma(rowbc<J>(src), mul, acc);
+}
+
+template <int k, int J>
+__device__ __forceinline__ void f16_a1(double (&a)[16], double nl, double akk) {
+    if constexpr (J > k) fmac_bc<J>(a[J], akk, nl);
+}
+template <int k, int J>
+__device__ __forceinline__ void f16_e1(double (&e)[16], double nle) {
+    if constexpr (J <= k) fmac_bc<k>(e[J], e[J], nle);
+}
+
+// Elimination step k of the LDL^T factorisation (unit lower factor U, pivots
+// d_k).  Lane i holds row i of the block (a) and row i of the running
+// transformation T (e, from the identity).  With u_ik = a_ik / d_k: rows
+// i > k take a_ij -= u_ik a_jk (j > k) and e_ij -= u_ik e_kj (j <= k); u_ik is
+// kept in a_ik.  1 / d_k is the hardware reciprocal r0 refined by Newton's
+// iteration, r1 = r0 (2 - d r0) and r2 = r1 (2 - d r1), with the last step
+// folded into its uses (u = a r1 + a r1 (1 - d r1)).  The next pivot is formed
+// straight from this one, d_{k+1} = a_{k+1,k+1} - a_{k+1,k}^2 / d_k, so the
+// chain from pivot to pivot is a few dependent operations; the broadcasts of
+// the a_jk do not wait for it.  After the last step a holds U below the
+// diagonal and e holds U^{-1}; `down` holds the lane's own pivot.
+template <int k, int... J>
+__device__ __forceinline__ void f16_step(double (&a)[16], double (&e)[16], double &down,
+                                         double &dnext, int i, bool &ok,
+                                         std::integer_sequence<int, J...>) {
+    const double d = rowbc<k>(dnext);
+    ok = ok && (d > 0.0) && isfinite(d);
+    const double r0 = __builtin_amdgcn_rcp(d);
+    const double e0 = __builtin_fma(-d, r0, 1.0);
+    const double r1 = __builtin_fma(r0, e0, r0);
+    const double e1 = __builtin_fma(-d, r1, 1.0);
+    const double akk = a[k];
+    const double m1 = akk * r1;
+    const double l = __builtin_fma(m1, e1, m1);
+    if constexpr (k + 1 < 16) {
+        const double t = akk * akk;
+        const double tr1 = t * r1;
+        const double u = __builtin_fma(-t, r1, a[k + 1]);
+        dnext = __builtin_fma(-tr1, e1, u);
+    }
+    (f16_a1<k, J>(a, -l, akk), ...);
+    const double nle = (i > k) ? -l : 0.0;   // transformation rows below the pivot only
+    (f16_e1<k, J>(e, nle), ...);
+    a[k] = (i == k) ? akk : l;
+    down = (i == k) ? d : down;
+}
+
+template <int J>
+__device__ __forceinline__ void f16_scale1(double (&a)[16], double sq) {
+    a[J] *= rowbc<J>(sq);
+}
+
+template <int... K>
+__device__ __forceinline__ void f16_steps(double (&a)[16], double (&e)[16], double &down, int i,
+                                          bool &ok, std::integer_sequence<int, K...>) {
+    double dnext = a[0];
+    (f16_step<K>(a, e, down, dnext, i, ok, std::make_integer_sequence<int, 16>{}), ...);
+}
+
+template <int... J>
+__device__ __forceinline__ void f16_scale(double (&a)[16], double sq,
+                                          std::integer_sequence<int, J...>) {
+    (f16_scale1<J>(a, sq), ...);
+}
+
 // Cholesky factor and inverse of a 16 x 16 SPD block in LDS (row stride RS) on
-// one wave, lane i & 15 holding row i: right-looking elimination with the
-// columns broadcast by readlane; the block is overwritten by L (zeros above
-// the diagonal) and Wl receives L^{-1}, column j by lane j (forward
-// substitution, the earlier columns applied as they are found).
+// one wave, lane i & 15 holding row i (every 16-lane row of the wave carries
+// the same copy), from the LDL^T elimination: L = U D^{1/2} and L^{-1} =
+// D^{-1/2} U^{-1}, with 1 / sqrt(d_i) from rsq_nr.  The block is overwritten
+// by L (zeros above the diagonal) and Wl receives L^{-1}.
 __device__ __forceinline__ void f16(double *S, int RS, double *Wl, bool &ok) {
     const int lane = threadIdx.x & 63, i = lane & 15;
-    double a[16], rk[16];
+    double a[16], e[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) a[j] = (j <= i) ? S[i * RS + j] : 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const double d = bcast64(a[k], k);
-        ok = ok && (d > 0.0) && isfinite(d);
-        const double r = rsq_nr(d);
-        rk[k] = r;
-        a[k] = (i == k) ? d * r : a[k] * r;
-#pragma unroll
-        for (int j = k + 1; j < 16; ++j) a[j] = __builtin_fma(-a[k], bcast64(a[k], j), a[j]);
+    for (int j = 0; j < 16; ++j) {
+        a[j] = (j <= i) ? S[i * RS + j] : 0.0;
+        e[j] = (j == i) ? 1.0 : 0.0;
     }
+    double down = 1.0;
+    f16_steps(a, e, down, i, ok, std::make_integer_sequence<int, 16>{});
+    const double s = rsq_nr(down), sq = down * s;   // 1 / sqrt(d_i), sqrt(d_i)
+    f16_scale(a, sq, std::make_integer_sequence<int, 16>{});   // u_ij sqrt(d_j)
     wsync();
     if (lane < 16) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) S[i * RS + j] = (j <= i) ? a[j] : 0.0;
-    }
-    wsync();
-    double acc[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = (r == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-        const double w = acc[c] * rk[c];
-        acc[c] = w;
-#pragma unroll
-        for (int r = c + 1; r < 16; ++r) acc[r] = __builtin_fma(-S[r * RS + c], w, acc[r]);
-    }
-    if (lane < 16) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) Wl[r * RS + i] = acc[r];
+        for (int j = 0; j < 16; ++j) {
+            S[i * RS + j] = (j < i) ? a[j] : ((j == i) ? sq : 0.0);
+            Wl[i * RS + j] = (j <= i) ? e[j] * s : 0.0;
+        }
     }
     wsync();
 }
@@ -406,10 +471,13 @@ __global__ __launch_bounds__(256) void k_big_xtx(const double *__restrict__ X, i
 }
 
 // Backward solve L^T y = z of the greedy system (one workgroup), z being the
-// right-hand-side row of the factor.  For each tile column p from the last:
-// t = z_p - sum_{k > p} L_kp^T y_k (thread (r, s) sums the rows s, s + 32, ...
-// of column r; the 32 row segments are added in order), then y_p = W_p^T t.
-// Every load of a step (its column block of L, W_p) is issued together.
+// right-hand-side row of the factor, two tile columns (lo = hi - 1, hi) per
+// step from the last: t = z_{lo,hi} - sum_{k > hi} L_k,{lo,hi}^T y_k (thread
+// (c, s) sums the rows s, s + 16, ... of column c of the 64-wide block; the 16
+// row segments are added in order), then y_hi = W_hi^T t_hi,
+// t_lo -= L_{hi,lo}^T y_hi and y_lo = W_lo^T t_lo.  Every load of a step (its
+// column block of L, W_hi, W_lo, L_{hi,lo}) is issued together.  With an odd
+// number of tile columns the first step (from the bottom) takes one.
 constexpr int BS_T = 1024;
 constexpr int BS_R = 32;   // rows per thread per round
 
@@ -419,44 +487,72 @@ __global__ __launch_bounds__(BS_T) void k_big_bsolve(const double *__restrict__ 
                                                      const Ctrl *__restrict__ ctrl) {
     if (ctrl_done(ctrl)) return;
     __shared__ double z[BIGB];
-    __shared__ double part[TB][TB + 1];
-    __shared__ double sWp[TB][TB + 1];
-    __shared__ double t[TB];
-    const int tid = threadIdx.x, r = tid & (TB - 1), sg = tid >> 5;
+    __shared__ double part[2 * TB][17];
+    __shared__ double sWh[TB][TB + 1], sWl[TB][TB + 1], sLhl[TB][TB + 1];
+    __shared__ double t[2 * TB];
+    const int tid = threadIdx.x, c = tid & (2 * TB - 1), sg = tid >> 6;
     for (int i = tid; i < P * TB; i += BS_T) z[i] = Lf[(int64_t)ld * ld + i];
     __syncthreads();
-    for (int p = P - 1; p >= 0; --p) {
-        const double wv = W[(int64_t)p * TB * TB + tid];
+    int hi = P - 1;
+    while (hi >= 0) {
+        const int lo = ((P - 1 - hi) == 0 && (P & 1)) ? -1 : hi - 1;   // odd P: single first step
+        const int c0 = (lo >= 0 ? lo : hi) * TB;                       // first column of the step
+        const int ncol = (lo >= 0) ? 2 * TB : TB;
+        const double wh = W[(int64_t)hi * TB * TB + tid];
+        const double wl = (lo >= 0) ? W[(int64_t)lo * TB * TB + tid] : 0.0;
+        const double lhl = (lo >= 0) ? Lf[(int64_t)(hi * TB + (tid >> 5)) * ld + lo * TB + (tid & 31)] : 0.0;
         double s = 0.0;
-        const int nr = P - p - 1;                 // tile rows below the diagonal
-        for (int u0 = 0; u0 < nr; u0 += BS_R) {
-            double gv[BS_R];
+        const int nr = (P - hi - 1) * TB;          // rows below the step's diagonal tiles
+        if (c < ncol) {
+            for (int u0 = 0; u0 < nr; u0 += 16 * BS_R) {
+                double gv[BS_R];
 #pragma unroll
-            for (int u = 0; u < BS_R; ++u) {
-                const int c = (p + 1 + u0 + u) * TB + sg;
-                gv[u] = (u0 + u < nr) ? Lf[(int64_t)c * ld + p * TB + r] : 0.0;
-            }
+                for (int u = 0; u < BS_R; ++u) {
+                    const int rr = u0 + sg + 16 * u;
+                    gv[u] = (rr < nr) ? Lf[(int64_t)((hi + 1) * TB + rr) * ld + c0 + c] : 0.0;
+                }
 #pragma unroll
-            for (int u = 0; u < BS_R; ++u) {
-                const int c = (p + 1 + u0 + u) * TB + sg;
-                if (u0 + u < nr) s = __builtin_fma(gv[u], z[c], s);
+                for (int u = 0; u < BS_R; ++u) {
+                    const int rr = u0 + sg + 16 * u;
+                    if (rr < nr) s = __builtin_fma(gv[u], z[(hi + 1) * TB + rr], s);
+                }
             }
         }
-        part[r][sg] = s;
-        sWp[tid >> 5][tid & 31] = wv;
+        part[c][sg] = s;
+        sWh[tid >> 5][tid & 31] = wh;
+        sWl[tid >> 5][tid & 31] = wl;
+        sLhl[tid >> 5][tid & 31] = lhl;
         __syncthreads();
-        if (tid < TB) {
-            double v = z[p * TB + tid];
-            for (int q2 = 0; q2 < TB; ++q2) v -= part[tid][q2];
-            t[tid] = v;
+        // the 16 segment sums of each column by a fixed butterfly (16 lanes per column)
+        {
+            const int cc = tid >> 4, q2 = tid & 15;
+            double v = group_sum(part[cc][q2], 16);
+            if (q2 == 0 && cc < ncol) t[cc] = z[c0 + cc] - v;
         }
         __syncthreads();
-        if (tid < TB) {
-            double v = 0.0;
-            for (int c = tid; c < TB; ++c) v = __builtin_fma(sWp[c][tid], t[c], v);
-            z[p * TB + tid] = v;
+        // 32 x 32 products below: output j by the 32 lanes (j, q), q summed by a
+        // fixed butterfly
+        const int oj = tid >> 5, oq = tid & 31;
+        const int oh = ncol - TB;
+        {   // y_hi = W_hi^T t_hi
+            const double v = group_sum(sWh[oq][oj] * t[oh + oq], 32);
+            if (oq == 0) z[hi * TB + oj] = v;
         }
         __syncthreads();
+        if (lo >= 0) {
+            {   // t_lo -= L_{hi,lo}^T y_hi
+                const double v = group_sum(sLhl[oq][oj] * z[hi * TB + oq], 32);
+                __syncthreads();
+                if (oq == 0) t[oj] -= v;
+            }
+            __syncthreads();
+            {   // y_lo = W_lo^T t_lo
+                const double v = group_sum(sWl[oq][oj] * t[oq], 32);
+                if (oq == 0) z[lo * TB + oj] = v;
+            }
+            __syncthreads();
+        }
+        hi = (lo >= 0) ? lo - 1 : hi - 1;
     }
     for (int i = tid; i < K; i += BS_T) y[i] = z[i];
 }
@@ -513,7 +609,7 @@ __global__ __launch_bounds__(256) void k_big_r(const int32_t *__restrict__ tau, 
 }
 
 // y = H_t r for the fixed block tau[tau_index] (H_t symmetric, read by rows),
-// 16 rows per workgroup, 16 lanes per row, fixed butterfly.  With gb set
+// 4 rows per workgroup, one wave per row, fixed butterfly.  With gb set
 // (adjoint), gb[S] -= y.
 template <typename V>
 __global__ __launch_bounds__(256) void k_big_y(const double *__restrict__ H,
@@ -530,26 +626,26 @@ __global__ __launch_bounds__(256) void k_big_y(const double *__restrict__ H,
     for (int j = threadIdx.x; j < cnt; j += blockDim.x) sr[j] = r[j];
     __syncthreads();
     const double *Hb = H + blk_hoff(t, q, rem);
-    const int i = blockIdx.x * 16 + (threadIdx.x >> 4), l = threadIdx.x & 15;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
     double s = 0.0;
     if (i < cnt) {
         const double *row = Hb + (int64_t)i * cnt;
-        constexpr int U = 16;
-        for (int jb = l; jb < cnt; jb += U * 16) {
+        constexpr int U = 8;
+        for (int jb = l; jb < cnt; jb += U * 64) {
             double hv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = jb + 16 * u;
+                const int j = jb + 64 * u;
                 hv[u] = (j < cnt) ? row[j] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int j = jb + 16 * u;
+                const int j = jb + 64 * u;
                 if (j < cnt) s = __builtin_fma(hv[u], sr[j], s);
             }
         }
     }
-    s = group_sum(s, 16);
+    s = group_sum(s, 64);
     if (i < cnt && l == 0) {
         y[i] = s;
         if (gb) gb[cst + i] -= (V)s;
@@ -698,6 +794,135 @@ __global__ __launch_bounds__(BIG_T) void k_big_apply(BigP p) {
     }
 }
 
+// ------------------------------------------------------------ greedy Gram --
+// Lower 32 x 32 tiles of A_I A_I^T (the greedy block's Gram) on FP64 MFMA for
+// large greedy sets: grid x = tiles, grid y = column chunks; each wave holds
+// the 16 x 16 sub-tiles of its tile over a quarter of the chunk's columns, so
+// every row value it loads feeds two MFMA products (half the cache traffic of
+// 16 x 16 tiles).  The four waves are summed in wave order.  Output: packed
+// lower partials Gpart[chunk][pk(i, j)].
+template <typename T, bool AL>
+__global__ __launch_bounds__(256) void k_gram32(const T *__restrict__ A, int64_t ld, int64_t n,
+                                                const int32_t *__restrict__ idx, int K, int64_t wg,
+                                                double *__restrict__ Gpart,
+                                                const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    constexpr int VW = Tr<T>::VW;
+    constexpr int E = (sizeof(T) == 8) ? 4 : VW;   // columns per lane per macro step
+    constexpr int NL = E / VW;                      // 16-byte loads per row per step
+    constexpr int U = (sizeof(T) == 8) ? 2 : 4;     // macro steps in flight
+    const int nt = (K + 31) / 32;
+    int bi, bj;
+    tile_of(blockIdx.x, nt, &bi, &bj);
+    const int64_t c0 = (int64_t)blockIdx.y * wg;
+    const int64_t c1 = (c0 + wg < n) ? c0 + wg : n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    const int64_t stepc = 4 * E;
+    const int64_t span = ((c1 - c0 + 4 * stepc - 1) / (4 * stepc)) * stepc;
+    const int64_t wa = c0 + w * span;
+    const int64_t wb = (wa + span < c1) ? wa + span : c1;
+    const bool same = (bi == bj);
+    const T *pa[2], *pb[2];
+    bool va[2], vb[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const int ia = bi * 32 + s2 * 16 + li, ib = bj * 32 + s2 * 16 + li;
+        va[s2] = ia < K;
+        vb[s2] = ib < K;
+        pa[s2] = A + (va[s2] ? (int64_t)idx[ia] : 0) * ld;
+        pb[s2] = A + (vb[s2] ? (int64_t)idx[ib] : 0) * ld;
+    }
+    const dvec4 z4 = {0.0, 0.0, 0.0, 0.0};
+    dvec4 acc[2][2] = {{z4, z4}, {z4, z4}};
+    const uvec4 zu = {0u, 0u, 0u, 0u};
+    for (int64_t c = wa; c < wb; c += 4 * E * U) {
+        uvec4 xa[U][2][NL], xb[U][2][NL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t col = c + (int64_t)u * 4 * E + (int64_t)g * E;
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                const int64_t cc = col + h * VW;
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    xa[u][s2][h] = (va[s2] && cc < wb) ? load_raw<T, AL>(pa[s2], cc, wb) : zu;
+                    xb[u][s2][h] = (!same && vb[s2] && cc < wb) ? load_raw<T, AL>(pb[s2], cc, wb) : zu;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int h = 0; h < NL; ++h) {
+                double a0[VW], a1[VW], b0[VW], b1[VW];
+                cvt_raw<T, double>(xa[u][0][h], a0);
+                cvt_raw<T, double>(xa[u][1][h], a1);
+                if (same) {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) { b0[e] = a0[e]; b1[e] = a1[e]; }
+                } else {
+                    cvt_raw<T, double>(xb[u][0][h], b0);
+                    cvt_raw<T, double>(xb[u][1][h], b1);
+                }
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[e], b0[e], acc[0][0], 0, 0, 0);
+                    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], b0[e], acc[1][0], 0, 0, 0);
+                    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[e], b1[e], acc[1][1], 0, 0, 0);
+                    if (!same)
+                        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[e], b1[e], acc[0][1], 0, 0, 0);
+                }
+            }
+    }
+    __shared__ double red[4][16][64];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[w][(s2 * 2 + t2) * 4 + r][lane] = acc[s2][t2][r];
+    __syncthreads();
+    if (w == 0) {
+        const int KP = K * (K + 1) / 2;
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q2 = (s2 * 2 + t2) * 4 + r;
+                    const double v = ((red[0][q2][lane] + red[1][q2][lane]) + red[2][q2][lane]) +
+                                     red[3][q2][lane];
+                    const int ii = bi * 32 + s2 * 16 + (lane >> 4) + 4 * r;
+                    const int jj = bj * 32 + t2 * 16 + li;
+                    if (ii < K && jj <= ii) Gpart[(int64_t)blockIdx.y * KP + pk(ii, jj)] = v;
+                }
+    }
+}
+
+template <typename T>
+static hipError_t gram32_typed(const rorbk_handle_s *h, const void *A, int aligned,
+                               const int32_t *idx, int K, double *Gpart, hipStream_t s) {
+    const Layout &L = h->L;
+    const int nt = (K + 31) / 32;
+    dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)L.nch_g);
+    if (aligned)
+        hipLaunchKernelGGL((k_gram32<T, true>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
+                           idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
+    else
+        hipLaunchKernelGGL((k_gram32<T, false>), grid, dim3(256), 0, s, (const T *)A, L.ld, L.n,
+                           idx, K, L.wg, Gpart, (const Ctrl *)h->d_ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_big(const rorbk_handle_s *h, const void *A, int dt, const int32_t *idx,
+                           int K, double *Gpart, hipStream_t s) {
+    const int al = h->aligned;
+    if (dt == RORBK_F64) return gram32_typed<double>(h, A, al, idx, K, Gpart, s);
+    if (dt == RORBK_F32) return gram32_typed<float>(h, A, al, idx, K, Gpart, s);
+    return gram32_typed<bf16_t>(h, A, al, idx, K, Gpart, s);
+}
+
 // ------------------------------------------------------------ launchers --
 // Factor `batch` padded matrices (rows x ld each, rows = ld or ld + TB) in
 // G: L into Lf, every diagonal tile's inverse into W[bt * P + p].
@@ -781,7 +1006,8 @@ static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hip
         hipLaunchKernelGGL(k_big_r<V>, dim3(g16), dim3(256), 0, s, h->d_tau, a.cur.tau_index,
                            L.q, L.rem, (const V *)a.b, a.Pin, (int)L.nch_u, (int)L.bmax,
                            h->d_bigr, (const Ctrl *)h->d_ctrl);
-        hipLaunchKernelGGL(k_big_y<V>, dim3(g16), dim3(256), 0, s, (const double *)h->d_H,
+        hipLaunchKernelGGL(k_big_y<V>, dim3((unsigned)((L.bmax + 3) / 4)), dim3(256), 0, s,
+                           (const double *)h->d_H,
                            h->d_tau, a.cur.tau_index, L.q, L.rem, (const double *)h->d_bigr,
                            h->d_bigy, (V *)a.gb, (const Ctrl *)h->d_ctrl);
         y = h->d_bigy;

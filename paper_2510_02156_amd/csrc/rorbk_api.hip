@@ -74,12 +74,12 @@ void plan_layout(Layout &L) {
     const bool big = L.format == RORBK_DENSE && L.bmax > RORBK_MAX_BLOCK_ROWS + 1;
     if (big) {
         // large blocks: one 128-column slab per update workgroup (row chunks
-        // add the rest of the parallelism); greedy Gram chunks sized so that
-        // tiles x chunks is about 4096 workgroups
+        // add the rest of the parallelism); greedy Gram (32 x 32 tiles) chunks
+        // sized so that tiles x chunks is about 1024 workgroups
         L.wu = 128;
         L.nch_u = (int32_t)((n + 127) / 128);
-        const int64_t nt = (L.K + 15) / 16, tiles = nt * (nt + 1) / 2;
-        int64_t nch = (4096 + tiles - 1) / tiles;
+        const int64_t nt = (L.K + 31) / 32, tiles = nt * (nt + 1) / 2;
+        int64_t nch = (1024 + tiles - 1) / tiles;
         if (nch > 64) nch = 64;
         if (nch > (n + 31) / 32) nch = (n + 31) / 32;
         if (nch < 1) nch = 1;
@@ -199,6 +199,7 @@ hipError_t gram(const rorbk_handle_s *h, const void *A, int dt, int aligned, con
                 int K, double *G) {
     (void)aligned;
     if (h->L.format == RORBK_CSR) return launch_gram_csr(h, A, dt, idx, K, G, h->stream);
+    if (K > RORBK_MAX_BLOCK_ROWS + 1) return launch_gram_big(h, A, dt, idx, K, G, h->stream);
     return launch_gram_dense(h, A, dt, idx, K, G, h->stream);
 }
 

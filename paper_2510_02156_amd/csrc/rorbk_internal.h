@@ -248,6 +248,8 @@ hipError_t launch_big_chol_solve(const rorbk_handle_s *h, const double *Gpart, i
                                  const double *rI, const double *Pin, double *y, hipStream_t s);
 hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, int64_t kp,
                                      int32_t *d_fail, hipStream_t s);
+hipError_t launch_gram_big(const rorbk_handle_s *h, const void *A, int dt, const int32_t *idx,
+                           int K, double *Gpart, hipStream_t s);
 
 // format-specific block step, residual products and greedy Gram
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
