@@ -156,8 +156,18 @@ int ror_bk_get_setup(rorbk_handle h, int64_t *offsets_host, double *S_host,
  * implementation's table so that sampled indices can be compared bit for bit. */
 int ror_bk_set_proposal(rorbk_handle h, const double *W_host);
 
-/* The stored inverse (A_t A_t^T + lambda I)^{-1} of block t, b_t x b_t
- * row-major doubles, into host memory. */
+/* Which form of the regularised block solve setup chose (Sec. 3.1): 0 for the
+ * row form, A_t^T (A_t A_t^T + lambda I)^{-1}, with b_t x b_t stored inverses;
+ * 1 for the column form, (A_t^T A_t + lambda I)^{-1} A_t^T, taken for dense
+ * blocks of more than RORBK_MAX_BLOCK_ROWS + 1 rows that have at least as many
+ * rows as columns, with n x n stored inverses.  Both compute the same update
+ * (Lemma 1); the adjoint (ror_bk_backward) is built for the row form only and
+ * returns RORBK_ERR_UNSUPPORTED on a column-form handle. */
+int ror_bk_get_form(rorbk_handle h, int32_t *column_form);
+
+/* The stored inverse of block t into host memory, row-major doubles: row
+ * form (A_t A_t^T + lambda I)^{-1}, b_t x b_t; column form
+ * (A_t^T A_t + lambda I)^{-1}, n x n. */
 int ror_bk_get_block_inverse(rorbk_handle h, int64_t t, double *Hinv_host);
 
 /* The block indices the sampler draws for iterations j0 .. j0+count-1

@@ -12,7 +12,8 @@ import torch
 from .binding import *  # noqa: F401,F403
 from .binding import (RORBK_CHECKPOINT, RORBK_PROFILE, RORBK_RECORD, RORBK_REFINE, RORBK_REPLAY,
                       RorBkError, lib, ror_bk_backward, ror_bk_destroy,
-                      ror_bk_get_block_inverse, ror_bk_get_profile, ror_bk_get_record,
+                      ror_bk_get_block_inverse, ror_bk_get_form, ror_bk_get_profile,
+                      ror_bk_get_record,
                       ror_bk_get_setup,
                       ror_bk_fabgmres, ror_bk_get_sizes, ror_bk_initial_solution,
                       ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
@@ -73,7 +74,16 @@ class Solver:
     def set_proposal(self, W):
         ror_bk_set_proposal(self.h, W)
 
+    @property
+    def column_form(self) -> bool:
+        """True if setup chose the column form (n x n stored inverses)."""
+        return ror_bk_get_form(self.h) == 1
+
     def block_inverse(self, t: int):
+        """Stored inverse of block t: (A_t A_t^T + lambda I)^{-1} (row form) or
+        (A_t^T A_t + lambda I)^{-1} (column form)."""
+        if self.column_form:
+            return ror_bk_get_block_inverse(self.h, t, self.n)
         off = self.setup_arrays()["offsets"]
         return ror_bk_get_block_inverse(self.h, t, int(off[t + 1] - off[t]))
 

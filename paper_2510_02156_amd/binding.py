@@ -34,7 +34,7 @@ RORBK_PROFILE = 16
 EXPORTS = [
     "ror_bk_setup", "ror_bk_solve", "ror_bk_backward", "ror_bk_destroy",
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
-    "ror_bk_get_block_inverse", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
+    "ror_bk_get_block_inverse", "ror_bk_get_form", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
     "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
     "ror_bk_get_profile", "ror_bk_initial_solution", "ror_bk_fabgmres", "ror_bk_error_string",
     "ror_bk_last_error_message",
@@ -90,6 +90,7 @@ def lib():
             "ror_bk_get_setup": (C.c_int, [P, P, P, P, P]),
             "ror_bk_set_proposal": (C.c_int, [P, P]),
             "ror_bk_get_block_inverse": (C.c_int, [P, I64, P]),
+            "ror_bk_get_form": (C.c_int, [P, P]),
             "ror_bk_sample": (C.c_int, [P, C.c_uint64, I64, I64, P]),
             "ror_bk_topk": (C.c_int, [P, P, I32, P]),
             "ror_bk_residual": (C.c_int, [P, P, P, P, P, I32, I32, P]),
@@ -218,6 +219,12 @@ def ror_bk_get_setup(h):
 def ror_bk_set_proposal(h, W):
     W = np.ascontiguousarray(W, dtype=np.float64)
     _check(lib().ror_bk_set_proposal(h, _np_ptr(W)), "ror_bk_set_proposal")
+
+
+def ror_bk_get_form(h) -> int:
+    col = C.c_int32()
+    _check(lib().ror_bk_get_form(h, C.byref(col)), "ror_bk_get_form")
+    return col.value
 
 
 def ror_bk_get_block_inverse(h, t: int, rows: int):

@@ -435,9 +435,10 @@ __global__ __launch_bounds__(256) void k_big_invrow(const double *__restrict__ L
 
 // Stored inverse of block t0 + bt: H = X^T X with H_IJ = sum_{k >= I} X_kI^T
 // X_kJ (J <= I, k order), written in full as the block's rows x rows row-major
-// array at its offset in H; the mirrored entries come from the lower ones.
+// array at its offset in H (fixedK > 0, column form: fixedK x fixedK at
+// t * fixedK^2); the mirrored entries come from the lower ones.
 __global__ __launch_bounds__(256) void k_big_xtx(const double *__restrict__ X, int ld, int P,
-                                                 int64_t t0, int64_t q, int64_t rem,
+                                                 int64_t t0, int64_t q, int64_t rem, int fixedK,
                                                  double *__restrict__ H) {
     __shared__ double sA[TB][TB + 1], sB[TB][TB + 1];
     const int bt = blockIdx.x, f = blockIdx.y;
@@ -457,8 +458,8 @@ __global__ __launch_bounds__(256) void k_big_xtx(const double *__restrict__ X, i
         __syncthreads();
     }
     const int64_t t = t0 + bt;
-    const int K = blk_rows(t, q, rem);
-    double *Hb = H + blk_hoff(t, q, rem);
+    const int K = fixedK > 0 ? fixedK : blk_rows(t, q, rem);
+    double *Hb = H + (fixedK > 0 ? t * (int64_t)fixedK * fixedK : blk_hoff(t, q, rem));
     const int r = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -666,6 +667,7 @@ struct BigP {
     RowSel nxt;
     double *Pout;         // [column chunk][bmax]
     int bmax;
+    const double *dx;     // column form: the step's correction (x_new = xold + dx)
     const Ctrl *ctrl;
 };
 
@@ -729,7 +731,8 @@ __global__ __launch_bounds__(BIG_T) void k_big_upd(BigP p) {
 }
 
 // Apply and next products: workgroup (w, rc) forms x_new[cols] = xold[cols] +
-// sum_rc' dxp[rc'][cols] (rc' order; x itself if there is no update), chunk
+// sum_rc' dxp[rc'][cols] (rc' order), or xold + dx for the column form (x
+// itself if there is no update), chunk
 // row 0 writes it to x, and every workgroup produces the partial products
 // Pout[w][i] = A[row_i, cols] . x_new[cols] of the next rows i in its chunk
 // (lane sums by a fixed butterfly).
@@ -766,7 +769,10 @@ __global__ __launch_bounds__(BIG_T) void k_big_apply(BigP p) {
         const int64_t c = c0 + tid;
         V xv = (V)0;
         if (c < c1) {
-            if (p.upd && cnt > 0) {
+            if (p.upd && p.dx) {
+                xv = ((const V *)p.xold)[c] + (V)p.dx[c];
+                if (blockIdx.y == 0) x[c] = xv;
+            } else if (p.upd && cnt > 0) {
                 const int nrc = (cnt + RCH - 1) / RCH;
                 V s = (V)0;
                 for (int rc = 0; rc < nrc; ++rc) s += ((const V *)p.dxp)[(int64_t)rc * p.n + c];
@@ -923,10 +929,166 @@ hipError_t launch_gram_big(const rorbk_handle_s *h, const void *A, int dt, const
     return gram32_typed<bf16_t>(h, A, al, idx, K, Gpart, s);
 }
 
+// ------------------------------------------------------------ column form --
+// For blocks with at least as many rows as columns the update uses the
+// column form of the regularised block solve (Sec. 3.1; Lemma 1 for the
+// regularised system): A_S^T (A_S A_S^T + lambda I)^{-1} r equals
+// (A_S^T A_S + lambda I)^{-1} A_S^T r, whose system is n x n instead of b x b.
+// Stored inverses M_t = (A_t^T A_t + lambda I)^{-1} (n x n, block t at t n^2);
+// a step forms g = A_S^T r_S (the update kernel with y = r_S), dx = M g, and
+// x += dx in the apply kernel.
+
+// Column Gram A_S^T A_S of a row set (lower 32 x 32 tiles of the n x n
+// result on FP64 MFMA): the rows of block t0 + blockIdx.z (idx == NULL) or the
+// gathered rows idx[0 .. cnt).  Grid x = tiles, y = row chunks of rch rows,
+// z = batch.  Each wave sums a quarter of the chunk's rows, four rows (the
+// MFMA's k) per step: lane (c, g) supplies row g of the step at column c of
+// the tile.  The four waves are summed in order.  Output: packed lower
+// partials G[(z * nchunk + chunk) * n(n+1)/2 + pk(i, j)].
+template <typename T>
+__global__ __launch_bounds__(256) void k_colgram(const T *__restrict__ A, int64_t ld, int n,
+                                                 const int32_t *__restrict__ idx, int cnt_g,
+                                                 int64_t t0, int64_t q, int64_t rem, int rch,
+                                                 int nchunk, double *__restrict__ G,
+                                                 const Ctrl *__restrict__ ctrl) {
+    if (ctrl_done(ctrl)) return;
+    constexpr int U = 4;   // row steps in flight
+    const int nt = (n + 31) / 32;
+    int bi, bj;
+    tile_of(blockIdx.x, nt, &bi, &bj);
+    int cnt;
+    int64_t rs = 0;
+    if (idx) {
+        cnt = cnt_g;
+    } else {
+        const int64_t t = t0 + blockIdx.z;
+        cnt = blk_rows(t, q, rem);
+        rs = blk_start(t, q, rem);
+    }
+    const int r0 = blockIdx.y * rch;
+    const int r1 = (r0 + rch < cnt) ? r0 + rch : cnt;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    const int nrw = ((r1 - r0 + 15) / 16) * 4;   // rows per wave, a multiple of 4
+    const int wr0 = r0 + w * nrw;
+    const int wr1 = (wr0 + nrw < r1) ? wr0 + nrw : r1;
+    const bool same = bi == bj;
+    const int ca[2] = {bi * 32 + li, bi * 32 + 16 + li};
+    const int cb[2] = {bj * 32 + li, bj * 32 + 16 + li};
+    const dvec4 z4 = {0.0, 0.0, 0.0, 0.0};
+    dvec4 acc[2][2] = {{z4, z4}, {z4, z4}};
+    for (int r = wr0; r < wr1; r += 4 * U) {
+        double xa[U][2], xb[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int rr = r + 4 * u + g;
+            const bool valid = rr < wr1;
+            const int64_t row = valid ? (idx ? (int64_t)idx[rr] : rs + rr) : 0;
+            const T *pr = A + row * ld;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                xa[u][s2] = (valid && ca[s2] < n) ? to_v<double>(pr[ca[s2]]) : 0.0;
+                xb[u][s2] = (!same && valid && cb[s2] < n) ? to_v<double>(pr[cb[s2]]) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double b0 = same ? xa[u][0] : xb[u][0];
+            const double b1 = same ? xa[u][1] : xb[u][1];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][0], b0, acc[0][0], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][1], b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][1], b1, acc[1][1], 0, 0, 0);
+            if (!same)
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][0], b1, acc[0][1], 0, 0, 0);
+        }
+    }
+    __shared__ double red[4][16][64];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[w][(s2 * 2 + t2) * 4 + r][lane] = acc[s2][t2][r];
+    __syncthreads();
+    if (w == 0) {
+        const int64_t KP = (int64_t)n * (n + 1) / 2;
+        double *out = G + ((int64_t)blockIdx.z * nchunk + blockIdx.y) * KP;
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q2 = (s2 * 2 + t2) * 4 + r;
+                    const double v = ((red[0][q2][lane] + red[1][q2][lane]) + red[2][q2][lane]) +
+                                     red[3][q2][lane];
+                    const int ii = bi * 32 + s2 * 16 + (lane >> 4) + 4 * r;
+                    const int jj = bj * 32 + t2 * 16 + li;
+                    if (ii < n && jj <= ii) out[pk(ii, jj)] = v;
+                }
+    }
+}
+
+// g_j = sum_rc dxp[rc][j] (rc order): A_I^T r_I from the update kernel's
+// row-chunk partials, the right-hand side of the greedy column system.
+template <typename V>
+__global__ __launch_bounds__(256) void k_col_sum(const V *__restrict__ dxp, int nrc, int n,
+                                                 double *__restrict__ g,
+                                                 const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int rc = 0; rc < nrc; ++rc) s += (double)dxp[(int64_t)rc * n + j];
+    g[j] = s;
+}
+
+// Fixed block t = tau[tau_index], column form: g = sum_rc dxp[rc] (rc order,
+// in LDS), dx = M_t g with one wave per row of M_t (symmetric, read by rows)
+// and a fixed butterfly; 4 rows per workgroup.
+template <typename V, int RCH>
+__global__ __launch_bounds__(256) void k_col_dx(const double *__restrict__ H,
+                                                const int32_t *__restrict__ tau, int64_t tau_index,
+                                                int64_t q, int64_t rem, int n,
+                                                const V *__restrict__ dxp, double *__restrict__ dx,
+                                                const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double sg[BIGB];
+    const int t = tau[tau_index];
+    const int nrc = (blk_rows(t, q, rem) + RCH - 1) / RCH;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double s = 0.0;
+        for (int rc = 0; rc < nrc; ++rc) s += (double)dxp[(int64_t)rc * n + j];
+        sg[j] = s;
+    }
+    __syncthreads();
+    const double *M = H + (int64_t)t * n * n;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    double s = 0.0;
+    if (i < n) {
+        const double *row = M + (int64_t)i * n;
+        constexpr int UU = 8;
+        for (int jb = l; jb < n; jb += UU * 64) {
+            double mv[UU];
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int j = jb + 64 * u;
+                mv[u] = (j < n) ? row[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UU; ++u) {
+                const int j = jb + 64 * u;
+                if (j < n) s = __builtin_fma(mv[u], sg[j], s);
+            }
+        }
+    }
+    s = group_sum(s, 64);
+    if (i < n && l == 0) dx[i] = s;
+}
+
 // ------------------------------------------------------------ launchers --
 // Factor `batch` padded matrices (rows x ld each, rows = ld or ld + TB) in
 // G: L into Lf, every diagonal tile's inverse into W[bt * P + p].
-static hipError_t big_potrf(double *G, double *Lf, int ld, int rows, int batch, double *W,
+hipError_t big_potrf(double *G, double *Lf, int ld, int rows, int batch, double *W,
                             int32_t *fail, Ctrl *ctrl, hipStream_t s) {
     const int P = ld / TB, PR = rows / TB;
     const int64_t ms = (int64_t)rows * ld;
@@ -968,7 +1130,7 @@ hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, 
             hipLaunchKernelGGL(k_big_invrow, dim3((unsigned)batch, I + 1), dim3(256), 0, s,
                                (const double *)Lf, ld, I, (const double *)W, P, X);
         hipLaunchKernelGGL(k_big_xtx, dim3((unsigned)batch, P * (P + 1) / 2), dim3(256), 0, s,
-                           (const double *)X, ld, P, t0, L.q, L.rem, h->d_H);
+                           (const double *)X, ld, P, t0, L.q, L.rem, 0, h->d_H);
         e = hipGetLastError();
     }
     if (G) (void)hipFreeAsync(G, s);
@@ -996,12 +1158,140 @@ hipError_t launch_big_chol_solve(const rorbk_handle_s *h, const double *Gpart, i
     return hipGetLastError();
 }
 
+// Column form, setup: M_t = (A_t^T A_t + lambda I)^{-1} for every block, in
+// batches: column Grams (row chunks of 256), padded unpack, factorisation,
+// L^{-1} by tile rows, M = L^{-T} L^{-1} at t n^2.
+template <typename T>
+static hipError_t col_inverses_typed(const rorbk_handle_s *h, const void *A, int32_t *d_fail,
+                                     hipStream_t s) {
+    const Layout &L = h->L;
+    const int n = (int)L.n;
+    const int P = (n + TB - 1) / TB, ld = P * TB;
+    const int64_t ms = (int64_t)ld * ld, KP = (int64_t)n * (n + 1) / 2;
+    const int rch = 256;
+    const int nchunk = (int)((L.bmax + rch - 1) / rch);
+    const int64_t per = (ms > (int64_t)nchunk * KP) ? ms : (int64_t)nchunk * KP;
+    int64_t bmaxb = ((int64_t)1 << 27) / per;
+    if (bmaxb < 1) bmaxb = 1;
+    if (bmaxb > L.k) bmaxb = L.k;
+    double *G = nullptr, *Lf = nullptr, *W = nullptr, *Gs = nullptr;
+    hipError_t e = hipMallocAsync((void **)&G, sizeof(double) * (size_t)(bmaxb * ms), s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&Lf, sizeof(double) * (size_t)(bmaxb * ms), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&W, sizeof(double) * (size_t)(bmaxb * P * TB * TB), s);
+    if (e == hipSuccess)
+        e = hipMallocAsync((void **)&Gs, sizeof(double) * (size_t)(bmaxb * nchunk * KP), s);
+    const unsigned tiles = (unsigned)(P * (P + 1) / 2);
+    for (int64_t t0 = 0; t0 < L.k && e == hipSuccess; t0 += bmaxb) {
+        const int batch = (int)((L.k - t0 < bmaxb) ? L.k - t0 : bmaxb);
+        hipLaunchKernelGGL(k_colgram<T>, dim3(tiles, (unsigned)nchunk, (unsigned)batch), dim3(256),
+                           0, s, (const T *)A, L.ld, n, (const int32_t *)nullptr, 0, t0, L.q,
+                           L.rem, rch, nchunk, Gs, (const Ctrl *)nullptr);
+        hipLaunchKernelGGL(k_big_unpack, dim3((unsigned)((ms + 255) / 256), (unsigned)batch),
+                           dim3(256), 0, s, (const double *)Gs, (int64_t)nchunk * KP, KP, nchunk,
+                           n, t0, L.q, L.rem, h->lambda, ld, ld, (const double *)nullptr,
+                           (const double *)nullptr, 0, 0, G, (const Ctrl *)nullptr);
+        e = big_potrf(G, Lf, ld, ld, batch, W, d_fail, nullptr, s);
+        if (e != hipSuccess) break;
+        double *X = G;
+        for (int I = 0; I < P; ++I)
+            hipLaunchKernelGGL(k_big_invrow, dim3((unsigned)batch, I + 1), dim3(256), 0, s,
+                               (const double *)Lf, ld, I, (const double *)W, P, X);
+        hipLaunchKernelGGL(k_big_xtx, dim3((unsigned)batch, P * (P + 1) / 2), dim3(256), 0, s,
+                           (const double *)X, ld, P, t0, L.q, L.rem, n, h->d_H);
+        e = hipGetLastError();
+    }
+    if (G) (void)hipFreeAsync(G, s);
+    if (Lf) (void)hipFreeAsync(Lf, s);
+    if (W) (void)hipFreeAsync(W, s);
+    if (Gs) (void)hipFreeAsync(Gs, s);
+    return e;
+}
+
+hipError_t launch_col_block_inverses(const rorbk_handle_s *h, const void *A, int dt,
+                                     int32_t *d_fail, hipStream_t s) {
+    if (dt == RORBK_F64) return col_inverses_typed<double>(h, A, d_fail, s);
+    if (dt == RORBK_F32) return col_inverses_typed<float>(h, A, d_fail, s);
+    return col_inverses_typed<bf16_t>(h, A, d_fail, s);
+}
+
+// Column form, greedy step: g = A_I^T r_I (update kernel over the gathered
+// rows with y = r_I, which also copies x for the apply kernel), the column
+// Gram of the gathered rows, then (A_I^T A_I + lambda I) dx = g by the padded
+// factorisation with g as its right-hand-side row and the backward solve.
+template <typename T, typename V>
+static hipError_t col_greedy_typed(const rorbk_handle_s *h, const void *A, int aligned, void *x,
+                                   const int32_t *I, int K, const double *rI, double *dx,
+                                   hipStream_t s) {
+    const Layout &L = h->L;
+    constexpr int RCH = big_rch<T>();
+    const int n = (int)L.n;
+    const int P = (n + TB - 1) / TB, ld = P * TB, rows = ld + TB;
+    const int64_t KP = (int64_t)n * (n + 1) / 2, el = (int64_t)rows * ld;
+    BigP p = {};
+    p.A = A;
+    p.ld = L.ld;
+    p.n = L.n;
+    p.q = L.q;
+    p.rem = L.rem;
+    p.tau = h->d_tau;
+    p.cur.kind = 1;
+    p.cur.count = K;
+    p.cur.idx = I;
+    p.upd = 1;
+    p.y = rI;
+    p.x = x;
+    p.xold = h->d_xold;
+    p.dxp = h->d_dxp;
+    p.nxt.kind = -1;
+    p.bmax = (int)L.bmax;
+    p.ctrl = h->d_ctrl;
+    const unsigned nrc = (unsigned)((K + RCH - 1) / RCH);
+    if (aligned)
+        hipLaunchKernelGGL((k_big_upd<T, V, true>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_big_upd<T, V, false>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
+    hipLaunchKernelGGL(k_colgram<T>, dim3((unsigned)(P * (P + 1) / 2), (unsigned)L.nch_g, 1),
+                       dim3(256), 0, s, (const T *)A, L.ld, n, I, K, (int64_t)0, L.q, L.rem,
+                       (int)L.wg, (int)L.nch_g, h->d_G, (const Ctrl *)h->d_ctrl);
+    hipLaunchKernelGGL(k_col_sum<V>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const V *)h->d_dxp, (int)nrc, n, h->d_bigr, (const Ctrl *)h->d_ctrl);
+    hipLaunchKernelGGL(k_big_unpack, dim3((unsigned)((el + 255) / 256), 1), dim3(256), 0, s,
+                       (const double *)h->d_G, (int64_t)0, KP, (int)L.nch_g, n, (int64_t)0, L.q,
+                       L.rem, h->lambda, ld, rows, (const double *)h->d_bigr,
+                       (const double *)nullptr, 0, 0, h->d_bigG, (const Ctrl *)h->d_ctrl);
+    hipError_t e = big_potrf(h->d_bigG, h->d_bigL, ld, rows, 1, h->d_bigW, nullptr, h->d_ctrl, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_big_bsolve, dim3(1), dim3(BS_T), 0, s, (const double *)h->d_bigL, ld, P,
+                       (const double *)h->d_bigW, n, dx, (const Ctrl *)h->d_ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_greedy(const rorbk_handle_s *h, const void *A, int dt, int aligned, int vec,
+                             void *x, const int32_t *I, int K, const double *rI, double *dx,
+                             hipStream_t s) {
+    if (vec == VEC_F64) return col_greedy_typed<double, double>(h, A, aligned, x, I, K, rI, dx, s);
+    if (dt == RORBK_F32) return col_greedy_typed<float, float>(h, A, aligned, x, I, K, rI, dx, s);
+    return col_greedy_typed<bf16_t, float>(h, A, aligned, x, I, K, rI, dx, s);
+}
+
 template <typename T, typename V>
 static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s) {
     const Layout &L = h->L;
     constexpr int RCH = big_rch<T>();
     const double *y = nullptr;
-    if (a.ymode == 0) {
+    const double *dx = nullptr;
+    if (h->col && a.ymode == 0) {
+        // column form: r_S, g partials (update kernel with y = r_S), dx = M_t g
+        const unsigned g16 = (unsigned)((L.bmax + 15) / 16);
+        hipLaunchKernelGGL(k_big_r<V>, dim3(g16), dim3(256), 0, s, h->d_tau, a.cur.tau_index,
+                           L.q, L.rem, (const V *)a.b, a.Pin, (int)L.nch_u, (int)L.bmax,
+                           h->d_bigr, (const Ctrl *)h->d_ctrl);
+        y = h->d_bigr;
+        dx = h->d_bigy;
+    } else if (h->col && a.ymode == 1) {
+        dx = a.ygiven;   // the greedy column solve ran the update kernel already
+    } else if (a.ymode == 0) {
         const unsigned g16 = (unsigned)((L.bmax + 15) / 16);
         hipLaunchKernelGGL(k_big_r<V>, dim3(g16), dim3(256), 0, s, h->d_tau, a.cur.tau_index,
                            L.q, L.rem, (const V *)a.b, a.Pin, (int)L.nch_u, (int)L.bmax,
@@ -1031,14 +1321,24 @@ static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hip
     p.nxt = a.nxt;
     p.Pout = a.Pout;
     p.bmax = (int)L.bmax;
+    p.dx = nullptr;
     p.ctrl = h->d_ctrl;
     const unsigned nrc = (unsigned)((L.bmax + RCH - 1) / RCH);
-    if (p.upd) {
+    if (h->col && a.ymode == 0) {
+        if (a.aligned)
+            hipLaunchKernelGGL((k_big_upd<T, V, true>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
+        else
+            hipLaunchKernelGGL((k_big_upd<T, V, false>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
+        hipLaunchKernelGGL((k_col_dx<V, RCH>), dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s,
+                           (const double *)h->d_H, h->d_tau, a.cur.tau_index, L.q, L.rem,
+                           (int)L.n, (const V *)h->d_dxp, h->d_bigy, (const Ctrl *)h->d_ctrl);
+    } else if (p.upd && !h->col) {
         if (a.aligned)
             hipLaunchKernelGGL((k_big_upd<T, V, true>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
         else
             hipLaunchKernelGGL((k_big_upd<T, V, false>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
     }
+    p.dx = dx;
     const unsigned nrc2 = (a.nxt.kind >= 0) ? nrc : 1u;
     if (a.aligned)
         hipLaunchKernelGGL((k_big_apply<T, V, true>), dim3(L.nch_u, nrc2), dim3(BIG_T), 0, s, p);

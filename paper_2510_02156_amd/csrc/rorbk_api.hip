@@ -69,10 +69,26 @@ bool aligned16(const void *p, int64_t ld, size_t es) {
 }
 
 // Column chunking of the block step, the greedy Gram and the selection.
-void plan_layout(Layout &L) {
+void plan_layout(Layout &L, bool col) {
     const int64_t n = L.n;
-    const bool big = L.format == RORBK_DENSE && L.bmax > RORBK_MAX_BLOCK_ROWS + 1;
-    if (big) {
+    const bool big = L.format == RORBK_DENSE && (L.bmax > RORBK_MAX_BLOCK_ROWS + 1 || col);
+    if (big && col) {
+        // column form: 128-column update slabs as for large blocks; the greedy
+        // column Gram splits the K gathered rows into chunks (multiples of 16
+        // rows) so that tiles x chunks is about 1024 workgroups
+        L.wu = 128;
+        L.nch_u = (int32_t)((n + 127) / 128);
+        const int64_t nt = (n + 31) / 32, tiles = nt * (nt + 1) / 2;
+        int64_t nch = (1024 + tiles - 1) / tiles;
+        const int64_t maxch = (L.K + 15) / 16;
+        if (nch > maxch) nch = maxch;
+        if (nch < 1) nch = 1;
+        int64_t wg = (L.K + nch - 1) / nch;
+        wg = ((wg + 15) / 16) * 16;
+        L.wg = wg;
+        L.nch_g = (int32_t)((L.K + wg - 1) / wg);
+        L.nseg = (int32_t)((n + 2047) / 2048);
+    } else if (big) {
         // large blocks: one 128-column slab per update workgroup (row chunks
         // add the rest of the parallelism); greedy Gram (32 x 32 tiles) chunks
         // sized so that tiles x chunks is about 1024 workgroups
@@ -331,8 +347,13 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
         sa.stop_test = 1;
         sa.skip_topk = 0;
         HIPCHK(launch_select(h, sa, s));
-        HIPCHK(gram(h, o.A, o.dt, o.aligned, h->d_I, (int)L.K, h->d_G));
-        HIPCHK(launch_chol_solve(h, h->d_G, (int)L.K, h->d_rI, nullptr, h->d_y, s));
+        if (h->col) {
+            HIPCHK(launch_col_greedy(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_I, (int)L.K,
+                                     h->d_rI, h->d_y, s));
+        } else {
+            HIPCHK(gram(h, o.A, o.dt, o.aligned, h->d_I, (int)L.K, h->d_G));
+            HIPCHK(launch_chol_solve(h, h->d_G, (int)L.K, h->d_rI, nullptr, h->d_y, s));
+        }
         a.cur.kind = 1;
         a.cur.count = (int32_t)L.K;
         a.cur.idx = h->d_I;
@@ -482,7 +503,11 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         }
         h->big = 1;
     }
-    plan_layout(L);
+    // column form (Sec. 3.1): blocks with at least as many rows as columns, in
+    // the large-block regime (smaller blocks keep the row form, whose systems
+    // are at most RORBK_MAX_BLOCK_ROWS + 1 square)
+    if (h->big && L.q >= L.n) h->col = 1;
+    plan_layout(L, h->col != 0);
     h->stream = (hipStream_t)stream;
     h->lambda = lambda;
     h->A = A->values;
@@ -505,7 +530,8 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
 
     const int64_t k = L.k, K = L.K, bmax = L.bmax;
     const int64_t q = L.q, rem = L.rem;
-    const int64_t htotal = rem * (q + 1) * (q + 1) + (k - rem) * q * q;
+    const int64_t htotal = h->col ? k * L.n * L.n : rem * (q + 1) * (q + 1) + (k - rem) * q * q;
+    const int64_t gdim = h->col ? L.n : K;   // size of the greedy system
     int rc = RORBK_OK;
 #define ALLOC(p, n)                                   \
     do {                                              \
@@ -541,13 +567,13 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_I, bmax);
     ALLOC(h->d_rI, bmax);
     ALLOC(h->d_y, bmax);
-    ALLOC(h->d_G, (int64_t)L.nch_g * K * (K + 1) / 2);
+    ALLOC(h->d_G, (int64_t)L.nch_g * gdim * (gdim + 1) / 2);
     ALLOC(h->d_red, 64);
     ALLOC(h->d_selcnt, 1);
     ALLOC(h->d_ysum, L.n);
     ALLOC(h->d_alg2, 3);
     if (h->big) {
-        const int64_t P = (K + 31) / 32;
+        const int64_t P = (gdim + 31) / 32;
         ALLOC(h->d_bigG, (P + 1) * 32 * P * 32);
         ALLOC(h->d_bigL, (P + 1) * 32 * P * 32);
         ALLOC(h->d_bigW, P * 32 * 32);
@@ -633,7 +659,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         hipError_t e1 = hipMemcpyAsync(d_fail, &zero, 4, hipMemcpyHostToDevice, s);
         hipError_t e2 = (L.format == RORBK_CSR)
                             ? launch_block_inverses_csr(h, h->A, L.dtype, d_fail, s)
-                            : launch_block_inverses_dense(h, h->A, L.dtype, h->aligned, d_fail, s);
+                            : (h->col ? launch_col_block_inverses(h, h->A, L.dtype, d_fail, s)
+                                      : launch_block_inverses_dense(h, h->A, L.dtype, h->aligned,
+                                                                    d_fail, s));
         hipError_t e3 = hipMemcpyAsync(&hfail, d_fail, 4, hipMemcpyDeviceToHost, s);
         hipError_t e4 = hipStreamSynchronize(s);
         dfree(d_fail);
@@ -641,8 +669,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
             return bail(fail(RORBK_ERR_HIP, "block inverse setup failed: %s",
                              hipGetErrorString(e2 != hipSuccess ? e2 : e4)));
         if (hfail)
-            return bail(fail(RORBK_ERR_NOT_SPD,
-                             "a block Gram A_t A_t^T + lambda I is not positive definite"));
+            return bail(fail(RORBK_ERR_NOT_SPD, h->col
+                             ? "a block Gram A_t^T A_t + lambda I is not positive definite"
+                             : "a block Gram A_t A_t^T + lambda I is not positive definite"));
     }
     *out = h;
     return RORBK_OK;
@@ -680,13 +709,23 @@ int ror_bk_set_proposal(rorbk_handle h, const double *W_host) {
     return RORBK_OK;
 }
 
+int ror_bk_get_form(rorbk_handle h, int32_t *column_form) {
+    if (!h || !column_form) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
+    *column_form = h->col;
+    return RORBK_OK;
+}
+
 int ror_bk_get_block_inverse(rorbk_handle h, int64_t t, double *Hinv_host) {
     if (!h || !Hinv_host) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
     const Layout &L = h->L;
     if (t < 0 || t >= L.k) return fail(RORBK_ERR_INVALID_ARG, "block %lld out of range", (long long)t);
     const int64_t big = std::min(t, L.rem);
-    const int64_t off = big * (L.q + 1) * (L.q + 1) + (t - big) * L.q * L.q;
-    const int64_t bt = L.q + (t < L.rem ? 1 : 0);
+    int64_t off = big * (L.q + 1) * (L.q + 1) + (t - big) * L.q * L.q;
+    int64_t bt = L.q + (t < L.rem ? 1 : 0);
+    if (h->col) {   // column form: (A_t^T A_t + lambda I)^{-1}, n x n
+        off = t * L.n * L.n;
+        bt = L.n;
+    }
     HIPCHK(hipMemcpyAsync(Hinv_host, h->d_H + off, 8 * bt * bt, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return RORBK_OK;
@@ -1251,6 +1290,10 @@ int ror_bk_backward(rorbk_handle h, const void *grad_x, void *grad_b, void *grad
     g_msg[0] = 0;
     if (!h || !grad_x || !grad_b || !grad_x0) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
     if (!h->rec_valid) return fail(RORBK_ERR_NOT_RECORDED, "no RECORD or CHECKPOINT solve to differentiate");
+    if (h->col)
+        return fail(RORBK_ERR_UNSUPPORTED,
+                    "the adjoint is built for the row form only (blocks with fewer rows than "
+                    "columns, or of at most %d rows)", RORBK_MAX_BLOCK_ROWS + 1);
     const Layout &L = h->L;
     hipStream_t s = h->stream;
     const int vec = h->rec_vec;

@@ -82,6 +82,8 @@ struct rorbk_handle_s {
     double *d_alg2;           // <b, A y>, ||A y||^2, coefficient
     // large-block path (dense blocks of more than RORBK_MAX_BLOCK_ROWS + 1 rows)
     int32_t big;              // 1 when the large-block kernels run the steps
+    int32_t col;              // 1: column form (blocks with at least as many rows as
+                              // columns): n x n stored inverses and greedy system
     double *d_bigG;           // greedy system, padded, with the right-hand-side row
     double *d_bigL;           // its Cholesky factor (same layout)
     double *d_bigW;           // inverses of its diagonal tiles
@@ -250,6 +252,13 @@ hipError_t launch_big_block_inverses(const rorbk_handle_s *h, const double *Gs, 
                                      int32_t *d_fail, hipStream_t s);
 hipError_t launch_gram_big(const rorbk_handle_s *h, const void *A, int dt, const int32_t *idx,
                            int K, double *Gpart, hipStream_t s);
+// column form: stored inverses (A_t^T A_t + lambda I)^{-1} and the greedy solve
+// dx = (A_I^T A_I + lambda I)^{-1} A_I^T r_I (also copies x for the apply kernel)
+hipError_t launch_col_block_inverses(const rorbk_handle_s *h, const void *A, int dt,
+                                     int32_t *d_fail, hipStream_t s);
+hipError_t launch_col_greedy(const rorbk_handle_s *h, const void *A, int dt, int aligned, int vec,
+                             void *x, const int32_t *I, int K, const double *rI, double *dx,
+                             hipStream_t s);
 
 // format-specific block step, residual products and greedy Gram
 hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);

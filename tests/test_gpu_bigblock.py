@@ -214,3 +214,110 @@ def test_big_limits():
     with pytest.raises(P.RorBkError) as ei:
         P.Solver(A, 2049, 1e-3)
     assert ei.value.code == P.RORBK_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------- column form
+# Blocks with at least as many rows as columns (and more than 161 rows) use the
+# column form (A_t^T A_t + lambda I)^{-1} A_t^T (Sec. 3.1); the oracle applies
+# the row form, which is the same operator (the push-through identity, pinned
+# on the CPU in test_oracle_pins.py), so it is the reference here.
+COL_CASES = [
+    (3000, 200, 300, 3e-4, "randn"),     # 10 blocks of 300 rows, n = 200
+    (2011, 170, 400, 4e-4, "svd"),       # blocks of 403/402 rows, n = 170 (ragged tiles)
+    (1500, 1, 300, 3e-4, "unif1"),       # one column
+]
+
+
+@pytest.mark.parametrize("m,n,br,lam,kind", COL_CASES)
+def test_col_setup_inverses(m, n, br, lam, kind):
+    s = system(m, n, kind, cfg=41)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    off = O.partition(m, br)
+    np.testing.assert_allclose(sol.setup_arrays()["S"], O.cosine_rowsums(s["A"], br), rtol=1e-12)
+    for t in sorted({0, sol.k // 2, sol.k - 1}):
+        At = s["A"][off[t]:off[t + 1]]
+        C = At.T @ At + lam * np.eye(n)
+        M = sol.block_inverse(t)
+        assert M.shape == (n, n)
+        np.testing.assert_array_equal(M, M.T)
+        e = rel(M, np.linalg.inv(C))
+        print(f"  column form block {t}: inverse rel err {e:.2e}", flush=True)
+        assert e < 50 * np.linalg.cond(C) * np.finfo(float).eps
+
+
+def noisy_rhs(s, cfg):
+    """b = A x* + noise: with blocks of at least n rows one regularised step
+    nearly solves a consistent system, leaving a residual at rounding level
+    whose top-K would be decided by rounding; an inconsistent right-hand side
+    keeps the residual, and so the greedy sets, well defined."""
+    return s["b"] + 0.1 * np.random.default_rng(cfg).standard_normal(s["A"].shape[0])
+
+
+@pytest.mark.parametrize("m,n,br,lam,kind", COL_CASES)
+def test_col_free_running_fp64(m, n, br, lam, kind):
+    s = system(m, n, kind, cfg=43)
+    b = noisy_rhs(s, 43)
+    iters = 8
+    ref = O.solve(s["A"], br, lam, b, seed=6, max_iters=iters)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, info = sol.solve(dev(b), seed=6, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"column form m={m} n={n} br={br}: rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+    np.testing.assert_allclose(rec["rrn"], ref["rrn_hist"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_col_low_precision_replay(storage):
+    m, n, br, lam = 2400, 150, 240, 2.4e-4
+    s = system(m, n, "svd", cfg=47)
+    if storage == "f32":
+        Av = s["A"].astype(np.float32).astype(np.float64)
+        At = dev(s["A"], torch.float32)
+    else:
+        Av = bf16_values(s["A"])
+        At = bf16_tensor(s["A"])
+    b = Av @ s["xstar"]
+    iters = 12
+    ref = O.solve(Av, br, lam, b, seed=4, max_iters=iters)
+    sol = P.Solver(At, br, lam)
+    sol.set_replay(ref["tau"], ref["I"], iters)
+    x, _ = sol.solve(dev(b, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
+    e = rel(host(x), ref["x"])
+    print(f"column form {storage}: rel err vs FP64 oracle {e:.2e}", flush=True)
+    assert e < 1e-4
+
+
+def test_col_stop_test_refine_and_fabgmres():
+    m, n, br = 4000, 250, 400
+    s = system(m, n, "randn", cfg=53)
+    lam = 1e-6 * br
+    ref = O.solve(s["A"], br, lam, s["b"], seed=3, tol=1e-8, max_iters=200)
+    sol = P.Solver(dev(s["A"]), br, lam)
+    x, info = sol.solve(dev(s["b"]), seed=3, tol=1e-8, max_iters=200)
+    print(f"column form stop test: oracle {ref['iters']} it, GPU {info['iters']} it", flush=True)
+    assert ref["converged"] and info["iters"] == ref["iters"] and info["converged"]
+    assert rel(host(x), ref["x"]) < 1e-10
+    A64 = dev(s["A"])
+    sm = P.Solver(A64.float(), br, lam, A64=A64)
+    xm, im = sm.solve(dev(s["b"]), seed=3, tol=1e-10, max_iters=400, refine=True)
+    rr = np.linalg.norm(s["b"] - s["A"] @ host(xm)) / np.linalg.norm(s["b"])
+    print(f"column form refine: FP64 rrn {rr:.2e}", flush=True)
+    assert im["converged"] and rr < 1e-10 * (1 + 1e-6)
+    kw = dict(seed=3, tol=1e-11, max_outer=5, inner_iters=2, eta=1e-2)
+    rg = O.fabgmres(s["A"], br, lam, s["b"], **kw)
+    xg, ig = sol.fabgmres(dev(s["b"]), **kw)
+    assert ig["outer"] == rg["outer"] and rel(host(xg), rg["x"]) < 1e-9
+
+
+def test_col_backward_refused():
+    m, n, br = 1200, 100, 200
+    s = system(m, n, "randn", cfg=59)
+    sol = P.Solver(dev(s["A"]), br, 2e-4)
+    x, _ = sol.solve(dev(s["b"]), seed=1, tol=0.0, max_iters=3, record=True)
+    with pytest.raises(P.RorBkError) as ei:
+        sol.backward(dev(np.ones(n)))
+    assert ei.value.code == P.RORBK_ERR_UNSUPPORTED
