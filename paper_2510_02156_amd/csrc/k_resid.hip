@@ -8,18 +8,19 @@ namespace rorbk {
 constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 
 // ------------------------------------------------------------ residual pass --
-// Algorithm 1, r = b - A x: the products (A x)_i over one 2048-column segment.
+// Algorithm 1, r = b - A x: the products (A x)_i over one 2048-column segment
+// (SW columns of it when the whole matrix is narrower, SW = 512 or 1024).
 // A persistent grid (two workgroups per CU) walks the rows: wave w takes rows
 // w*ROWS .. w*ROWS+ROWS-1, then the same rows plus nwaves*ROWS, and so on.
 // For each group of ROWS rows every 16-byte load of the group is issued
 // (non-temporal, raw bytes) before any of them is converted or used, so each
-// wave keeps ROWS * SEG * sizeof(T) bytes in flight; then each row's lane
-// sums (FMA in column order) are combined by a fixed butterfly.  Each lane
-// keeps its entries of x in registers.  Rows past the end re-read the last
-// row (in bounds) and discard the result.  axp[seg][i] = partial (A x)_i; the
-// selection kernel subtracts the segment sum from b.  Grid: x = workgroups,
-// y = segments.
-template <typename T, typename V, bool AL, int ROWS>
+// wave keeps ROWS * SW * sizeof(T) bytes in flight (narrow matrices take more
+// rows at a time); then each row's lane sums (FMA in column order) are
+// combined by a fixed butterfly.  Each lane keeps its entries of x in
+// registers.  Rows past the end re-read the last row (in bounds) and discard
+// the result.  axp[seg][i] = partial (A x)_i; the selection kernel subtracts
+// the segment sum from b.  Grid: x = workgroups, y = segments.
+template <typename T, typename V, bool AL, int ROWS, int SW>
 __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
                                                      const V *__restrict__ x,
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
                                                      const Ctrl *__restrict__ ctrl) {
     if (ctrl && ctrl->done) return;
     constexpr int VW = Tr<T>::VW;
-    constexpr int NVL = SEG / (WAVE * VW);
+    constexpr int NVL = SW / (WAVE * VW);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t seg = blockIdx.y;
     const int64_t c0 = seg * SEG;
@@ -68,9 +69,10 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
     }
 }
 
-template <typename T, typename V, int ROWS>
+template <typename T, typename V, int ROWS, int SW>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
                               const void *x, double *axp, hipStream_t s) {
+    static_assert(SW == SEG || SW == 512 || SW == 1024, "segment width");
     const Layout &L = h->L;
     // persistent grid: 2 workgroups (8 waves) per CU over all segments, fewer
     // for short matrices; with many segments (wide matrices) each wave keeps
@@ -81,25 +83,36 @@ static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligne
     if (groups > cap) groups = cap;
     dim3 grid((unsigned)groups, (unsigned)L.nseg);
     if (aligned)
-        hipLaunchKernelGGL((k_resid_dense<T, V, true, ROWS>), grid, dim3(256), 0, s, (const T *)A,
+        hipLaunchKernelGGL((k_resid_dense<T, V, true, ROWS, SW>), grid, dim3(256), 0, s, (const T *)A,
                            L.ld, L.m, L.n, (const V *)x, axp, (const Ctrl *)h->d_ctrl);
     else
-        hipLaunchKernelGGL((k_resid_dense<T, V, false, ROWS>), grid, dim3(256), 0, s,
+        hipLaunchKernelGGL((k_resid_dense<T, V, false, ROWS, SW>), grid, dim3(256), 0, s,
                            (const T *)A, L.ld, L.m, L.n, (const V *)x, axp,
                            (const Ctrl *)h->d_ctrl);
     return hipGetLastError();
 }
 
+// About sixteen 16-byte loads in flight per wave: rows per group chosen from
+// the loads one row takes (the segment width over 64 lanes x 16 bytes).
 hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt, int aligned,
                                  int vec, const void *x, double *axp, hipStream_t s) {
+    const int64_t n = h->L.n;
     if (vec == VEC_F64) {
         if (dt != RORBK_F64) return hipErrorInvalidValue;
+        if (n <= 512) return resid_typed<double, double, 4, 512>(h, A, aligned, x, axp, s);
+        if (n <= 1024) return resid_typed<double, double, 2, 1024>(h, A, aligned, x, axp, s);
         // the unaligned FP64 form needs twice the registers per row in flight
-        if (aligned) return resid_typed<double, double, 2>(h, A, aligned, x, axp, s);
-        return resid_typed<double, double, 1>(h, A, aligned, x, axp, s);
+        if (aligned) return resid_typed<double, double, 2, SEG>(h, A, aligned, x, axp, s);
+        return resid_typed<double, double, 1, SEG>(h, A, aligned, x, axp, s);
     }
-    if (dt == RORBK_F32) return resid_typed<float, float, 2>(h, A, aligned, x, axp, s);
-    return resid_typed<bf16_t, float, 2>(h, A, aligned, x, axp, s);
+    if (dt == RORBK_F32) {
+        if (n <= 512) return resid_typed<float, float, 8, 512>(h, A, aligned, x, axp, s);
+        if (n <= 1024) return resid_typed<float, float, 4, 1024>(h, A, aligned, x, axp, s);
+        return resid_typed<float, float, 2, SEG>(h, A, aligned, x, axp, s);
+    }
+    if (n <= 512) return resid_typed<bf16_t, float, 16, 512>(h, A, aligned, x, axp, s);
+    if (n <= 1024) return resid_typed<bf16_t, float, 8, 1024>(h, A, aligned, x, axp, s);
+    return resid_typed<bf16_t, float, 4, SEG>(h, A, aligned, x, axp, s);
 }
 
 }  // namespace rorbk

@@ -286,13 +286,16 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     ping ^= 1;
 
     const int64_t poll = 16;
+    // residual-pass timings (iteration, ms); launches after the stopping
+    // iteration return at once and are left out when the solve ends
     int timed_slot[2] = {0, 0};
+    int64_t timed_it[2] = {0, 0};
+    std::vector<std::pair<int64_t, float>> timings;
     auto take_time = [&](int slot) -> int {
         if (!timed_slot[slot]) return RORBK_OK;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->evr[slot][0], h->evr[slot][1]));
-        h->prof_in_ms += ms;
-        h->prof_in_n += 1;
+        timings.emplace_back(timed_it[slot], ms);
         timed_slot[slot] = 0;
         return RORBK_OK;
     };
@@ -328,6 +331,7 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
         if (timed) {
             HIPCHK(hipEventRecord(h->evr[chunk & 1][1], s));
             timed_slot[chunk & 1] = 1;
+            timed_it[chunk & 1] = it;
         }
         SelectArgs sa;
         memset(&sa, 0, sizeof(sa));
@@ -394,6 +398,11 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
                                   ? "non-finite residual at iteration %lld"
                                   : "block Gram not positive definite at iteration %lld",
                     (long long)c.last_it);
+    for (const auto &tm : timings)
+        if (!c.done || tm.first <= c.conv_it) {
+            h->prof_in_ms += tm.second;
+            h->prof_in_n += 1;
+        }
     if (c.done) {
         *ran = c.conv_it - it0 + 1;
         *stopped = true;

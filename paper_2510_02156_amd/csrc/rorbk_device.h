@@ -116,11 +116,22 @@ __device__ __forceinline__ void load_vec_nt(const T *__restrict__ row, int64_t c
 }
 
 // 16 raw bytes (VW elements) of a row at column c; elements at or past `lim`
-// read as zero.  ALIGNED as for load_vec.
+// read as zero.  ALIGNED as for load_vec.  Otherwise a full vector whose
+// address is 8-byte aligned (rows of 16- or 32-bit values whose stride is a
+// multiple of 8 bytes) is read as two 8-byte loads, anything else element by
+// element.
 template <typename T, bool ALIGNED>
 __device__ __forceinline__ uvec4 load_raw(const T *__restrict__ row, int64_t c, int64_t lim) {
     constexpr int VW = Tr<T>::VW;
     if (ALIGNED && c + VW <= lim) return *reinterpret_cast<const uvec4 *>(row + c);
+    if constexpr (!ALIGNED && sizeof(T) < 8) {
+        if (c + VW <= lim && (reinterpret_cast<uintptr_t>(row + c) & 7) == 0) {
+            const uint2 lo = *reinterpret_cast<const uint2 *>(row + c);
+            const uint2 hi = *reinterpret_cast<const uint2 *>(row + c + VW / 2);
+            const uvec4 v = {lo.x, lo.y, hi.x, hi.y};
+            return v;
+        }
+    }
     uvec4 w = {0u, 0u, 0u, 0u};
     if constexpr (sizeof(T) == 8) {
 #pragma unroll
