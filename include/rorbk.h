@@ -161,8 +161,7 @@ int ror_bk_set_proposal(rorbk_handle h, const double *W_host);
  * 1 for the column form, (A_t^T A_t + lambda I)^{-1} A_t^T, taken for dense
  * blocks of more than RORBK_MAX_BLOCK_ROWS + 1 rows that have at least as many
  * rows as columns, with n x n stored inverses.  Both compute the same update
- * (Lemma 1); the adjoint (ror_bk_backward) is built for the row form only and
- * returns RORBK_ERR_UNSUPPORTED on a column-form handle. */
+ * (Lemma 1), and ror_bk_backward differentiates either. */
 int ror_bk_get_form(rorbk_handle h, int32_t *column_form);
 
 /* The stored inverse of block t into host memory, row-major doubles: row

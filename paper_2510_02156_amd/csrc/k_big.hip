@@ -1085,6 +1085,74 @@ __global__ __launch_bounds__(256) void k_col_dx(const double *__restrict__ H,
     if (i < n && l == 0) dx[i] = s;
 }
 
+// Column form, adjoint.  The adjoint of a step needs y = -(A_S A_S^T +
+// lambda I)^{-1} A_S g' (g' the incoming cotangent of x), which the column
+// form gives as y = -A_S v with v = (A_S^T A_S + lambda I)^{-1} g'.
+// v = M_t g' for the fixed block tau[tau_index]: g' in LDS (as FP64), one wave
+// per row of M_t, fixed butterfly.
+template <typename V>
+__global__ __launch_bounds__(256) void k_col_mv(const double *__restrict__ H,
+                                                const int32_t *__restrict__ tau, int64_t tau_index,
+                                                int n, const V *__restrict__ gx,
+                                                double *__restrict__ v,
+                                                const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double sg[BIGB];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) sg[j] = (double)gx[j];
+    __syncthreads();
+    const int t = tau[tau_index];
+    const double *M = H + (int64_t)t * n * n;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    double s = 0.0;
+    if (i < n) {
+        const double *row = M + (int64_t)i * n;
+        for (int j = l; j < n; j += 64) s = __builtin_fma(row[j], sg[j], s);
+    }
+    s = group_sum(s, 64);
+    if (i < n && l == 0) v[i] = s;
+}
+
+// y_i = -(A_S v)_i for the rows of a step (one wave per row, v in LDS, fixed
+// butterfly), and gb[row_i] -= y_i.
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_col_av(const T *__restrict__ A, int64_t ld, int n,
+                                                RowSel rs, const int32_t *__restrict__ tau,
+                                                int64_t q, int64_t rem,
+                                                const double *__restrict__ v,
+                                                double *__restrict__ y, V *__restrict__ gb,
+                                                const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    __shared__ double sv[BIGB];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) sv[j] = v[j];
+    __syncthreads();
+    int cnt;
+    int64_t cst;
+    sel_rows(rs, tau, q, rem, &cnt, &cst);
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    double s = 0.0;
+    int64_t row = 0;
+    if (i < cnt) {
+        row = sel_row(rs, cst, i);
+        const T *pr = A + row * ld;
+        for (int j = l; j < n; j += 64) s = __builtin_fma(to_v<double>(pr[j]), sv[j], s);
+    }
+    s = group_sum(s, 64);
+    if (i < cnt && l == 0) {
+        y[i] = -s;
+        gb[row] += (V)s;
+    }
+}
+
+// g'_j as FP64, the right-hand side of the greedy column system in the adjoint.
+template <typename V>
+__global__ __launch_bounds__(256) void k_to_f64(const V *__restrict__ src, int n,
+                                                double *__restrict__ dst,
+                                                const Ctrl *__restrict__ ctrl) {
+    if (ctrl->done) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) dst[j] = (double)src[j];
+}
+
 // ------------------------------------------------------------ launchers --
 // Factor `batch` padded matrices (rows x ld each, rows = ld or ld + TB) in
 // G: L into Lf, every diagonal tile's inverse into W[bt * P + p].
@@ -1275,6 +1343,51 @@ hipError_t launch_col_greedy(const rorbk_handle_s *h, const void *A, int dt, int
     return col_greedy_typed<bf16_t, float>(h, A, aligned, x, I, K, rI, dx, s);
 }
 
+// Column form, adjoint of one step: v = M g' (fixed block: stored M_t; greedy
+// set: the factorised column system with g' as its right-hand side), then
+// y = -A_S v and gb[S] -= y into yout.  The caller then applies x += A_S^T y.
+template <typename T, typename V>
+static hipError_t col_adj_typed(const rorbk_handle_s *h, const RowSel &rs, const void *gx,
+                                void *gb, double *yout, hipStream_t s) {
+    const Layout &L = h->L;
+    const int n = (int)L.n;
+    const int P = (n + TB - 1) / TB, ld = P * TB, rows = ld + TB;
+    const int64_t KP = (int64_t)n * (n + 1) / 2, el = (int64_t)rows * ld;
+    if (rs.kind == 0) {
+        hipLaunchKernelGGL(k_col_mv<V>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s,
+                           (const double *)h->d_H, h->d_tau, rs.tau_index, n, (const V *)gx,
+                           h->d_bigy, (const Ctrl *)h->d_ctrl);
+    } else {
+        hipLaunchKernelGGL(k_colgram<T>, dim3((unsigned)(P * (P + 1) / 2), (unsigned)L.nch_g, 1),
+                           dim3(256), 0, s, (const T *)h->A, L.ld, n, rs.idx, rs.count,
+                           (int64_t)0, L.q, L.rem, (int)L.wg, (int)L.nch_g, h->d_G,
+                           (const Ctrl *)h->d_ctrl);
+        hipLaunchKernelGGL(k_to_f64<V>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const V *)gx, n, h->d_bigr, (const Ctrl *)h->d_ctrl);
+        hipLaunchKernelGGL(k_big_unpack, dim3((unsigned)((el + 255) / 256), 1), dim3(256), 0, s,
+                           (const double *)h->d_G, (int64_t)0, KP, (int)L.nch_g, n, (int64_t)0,
+                           L.q, L.rem, h->lambda, ld, rows, (const double *)h->d_bigr,
+                           (const double *)nullptr, 0, 0, h->d_bigG, (const Ctrl *)h->d_ctrl);
+        hipError_t e = big_potrf(h->d_bigG, h->d_bigL, ld, rows, 1, h->d_bigW, nullptr,
+                                 h->d_ctrl, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_big_bsolve, dim3(1), dim3(BS_T), 0, s, (const double *)h->d_bigL, ld,
+                           P, (const double *)h->d_bigW, n, h->d_bigy, (const Ctrl *)h->d_ctrl);
+    }
+    hipLaunchKernelGGL((k_col_av<T, V>), dim3((unsigned)((L.bmax + 3) / 4)), dim3(256), 0, s,
+                       (const T *)h->A, L.ld, n, rs, (const int32_t *)h->d_tau, L.q, L.rem,
+                       (const double *)h->d_bigy, yout, (V *)gb, (const Ctrl *)h->d_ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_adjoint(const rorbk_handle_s *h, const RowSel &rs, int vec, const void *gx,
+                              void *gb, double *yout, hipStream_t s) {
+    const int dt = h->L.dtype;
+    if (vec == VEC_F64) return col_adj_typed<double, double>(h, rs, gx, gb, yout, s);
+    if (dt == RORBK_F32) return col_adj_typed<float, float>(h, rs, gx, gb, yout, s);
+    return col_adj_typed<bf16_t, float>(h, rs, gx, gb, yout, s);
+}
+
 template <typename T, typename V>
 static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s) {
     const Layout &L = h->L;
@@ -1291,6 +1404,8 @@ static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hip
         dx = h->d_bigy;
     } else if (h->col && a.ymode == 1) {
         dx = a.ygiven;   // the greedy column solve ran the update kernel already
+    } else if (a.ymode == 3) {
+        y = a.ygiven;    // y given, update x += A_S^T y through the column partials
     } else if (a.ymode == 0) {
         const unsigned g16 = (unsigned)((L.bmax + 15) / 16);
         hipLaunchKernelGGL(k_big_r<V>, dim3(g16), dim3(256), 0, s, h->d_tau, a.cur.tau_index,
@@ -1312,7 +1427,7 @@ static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hip
     p.rem = L.rem;
     p.tau = h->d_tau;
     p.cur = a.cur;
-    p.upd = (a.ymode != 2) ? 1 : 0;
+    p.upd = (a.ymode != 2) ? 1 : 0;   // ymode 3: gb was updated with y already
     p.y = y;
     p.x = a.x;
     p.xold = h->d_xold;
@@ -1332,7 +1447,7 @@ static hipError_t big_step_typed(const rorbk_handle_s *h, const StepArgs &a, hip
         hipLaunchKernelGGL((k_col_dx<V, RCH>), dim3((unsigned)((L.n + 3) / 4)), dim3(256), 0, s,
                            (const double *)h->d_H, h->d_tau, a.cur.tau_index, L.q, L.rem,
                            (int)L.n, (const V *)h->d_dxp, h->d_bigy, (const Ctrl *)h->d_ctrl);
-    } else if (p.upd && !h->col) {
+    } else if (p.upd && (!h->col || a.ymode == 3)) {
         if (a.aligned)
             hipLaunchKernelGGL((k_big_upd<T, V, true>), dim3(L.nch_u, nrc), dim3(BIG_T), 0, s, p);
         else

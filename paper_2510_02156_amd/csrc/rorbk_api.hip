@@ -1270,7 +1270,12 @@ int backward_range(rorbk_handle_s *h, int64_t a, int64_t bnd, bool last_conv_in_
     for (size_t i = 0; i < steps.size(); ++i) {
         const St &st = steps[i];
         sa.cur = st.r;
-        if (st.greedy) {
+        if (h->col) {
+            // column form: y = -A_S (A_S^T A_S + lambda I)^{-1} g, gb[S] -= y
+            HIPCHK(launch_col_adjoint(h, st.r, vec, g, gb, h->d_bigr, s));
+            sa.ymode = 3;
+            sa.ygiven = h->d_bigr;
+        } else if (st.greedy) {
             HIPCHK(gram(h, h->A, L.dtype, h->aligned, st.r.idx, (int)L.K, h->d_G));
             HIPCHK(launch_chol_solve(h, h->d_G, (int)L.K, nullptr, h->d_P[ping], h->d_y, s));
             sa.ymode = 1;
@@ -1299,10 +1304,7 @@ int ror_bk_backward(rorbk_handle h, const void *grad_x, void *grad_b, void *grad
     g_msg[0] = 0;
     if (!h || !grad_x || !grad_b || !grad_x0) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
     if (!h->rec_valid) return fail(RORBK_ERR_NOT_RECORDED, "no RECORD or CHECKPOINT solve to differentiate");
-    if (h->col)
-        return fail(RORBK_ERR_UNSUPPORTED,
-                    "the adjoint is built for the row form only (blocks with fewer rows than "
-                    "columns, or of at most %d rows)", RORBK_MAX_BLOCK_ROWS + 1);
+
     const Layout &L = h->L;
     hipStream_t s = h->stream;
     const int vec = h->rec_vec;

@@ -185,7 +185,9 @@ struct StepArgs {
     void *x;              // iterate (vector type)
     void *gb;             // adjoint: dL/db accumulator (vector type) or NULL
     RowSel cur;           // step applied
-    int ymode;            // 0: y from partials + stored inverse; 1: y given; 2: none
+    int ymode;            // 0: y from partials + stored inverse; 1: y given (column
+                          // form: the correction dx given); 2: none; 3: y given,
+                          // x += A_S^T y in either form (column-form adjoint)
     const double *Pin;    // partials of the current step
     const double *ygiven;
     RowSel nxt;           // rows whose partial products are produced
@@ -256,6 +258,10 @@ hipError_t launch_gram_big(const rorbk_handle_s *h, const void *A, int dt, const
 // dx = (A_I^T A_I + lambda I)^{-1} A_I^T r_I (also copies x for the apply kernel)
 hipError_t launch_col_block_inverses(const rorbk_handle_s *h, const void *A, int dt,
                                      int32_t *d_fail, hipStream_t s);
+// column form, adjoint of one step: y = -A_S (A_S^T A_S + lambda I)^{-1} g' and
+// gb[S] -= y (the caller then applies x += A_S^T y with ymode 3)
+hipError_t launch_col_adjoint(const rorbk_handle_s *h, const RowSel &rs, int vec, const void *gx,
+                              void *gb, double *yout, hipStream_t s);
 hipError_t launch_col_greedy(const rorbk_handle_s *h, const void *A, int dt, int aligned, int vec,
                              void *x, const int32_t *I, int K, const double *rI, double *dx,
                              hipStream_t s);

@@ -313,11 +313,28 @@ def test_col_stop_test_refine_and_fabgmres():
     assert ig["outer"] == rg["outer"] and rel(host(xg), rg["x"]) < 1e-9
 
 
-def test_col_backward_refused():
-    m, n, br = 1200, 100, 200
-    s = system(m, n, "randn", cfg=59)
-    sol = P.Solver(dev(s["A"]), br, 2e-4)
-    x, _ = sol.solve(dev(s["b"]), seed=1, tol=0.0, max_iters=3, record=True)
-    with pytest.raises(P.RorBkError) as ei:
-        sol.backward(dev(np.ones(n)))
-    assert ei.value.code == P.RORBK_ERR_UNSUPPORTED
+@pytest.mark.parametrize("checkpoint", [False, True])
+def test_col_backward_matches_oracle(checkpoint):
+    """The adjoint through column-form steps: y = -A_S (A_S^T A_S + lambda I)^{-1}
+    g equals the row form's -(A_S A_S^T + lambda I)^{-1} A_S g (Lemma 1), so the
+    oracle's row-form adjoint is the reference."""
+    m, n, br, lam = 1200, 100, 200, 2e-3
+    s = system(m, n, "svd", cfg=59)
+    b = noisy_rhs(s, 59)
+    rng = np.random.default_rng(8)
+    x0, xt = rng.standard_normal(n), rng.standard_normal(n)
+    iters = 6
+    sol = P.Solver(dev(s["A"]), br, lam)
+    assert sol.column_form
+    x, _ = sol.solve(dev(b), dev(x0), seed=1, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    if checkpoint:   # the greedy sets are recomputed from checkpoints in backward
+        x2, _ = sol.solve(dev(b), dev(x0), seed=1, tol=0.0, max_iters=iters, checkpoint_every=4)
+        assert torch.equal(x, x2)
+    g = 2 * (host(x) - xt)
+    gb, gx0 = sol.backward(dev(g))
+    rb, rx0 = O.backward(s["A"], br, lam, rec["tau"], rec["I"], iters, False, g)
+    eb, ex = rel(host(gb), rb), rel(host(gx0), rx0)
+    print(f"column-form adjoint ({'checkpoint' if checkpoint else 'record'}): dL/db {eb:.2e}, "
+          f"dL/dx0 {ex:.2e}", flush=True)
+    assert eb < 1e-10 and ex < 1e-10

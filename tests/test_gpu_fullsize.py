@@ -108,3 +108,77 @@ def test_dense_2000x200_whole_cap():
     # free running reaches the same draws (generated up front from W)
     x2, _ = sol.solve(dev(w["b"]), seed=seed, tol=w["tol"], max_iters=50, record=True)
     np.testing.assert_array_equal(sol.record()["tau"], ref["tau"][:150])
+
+
+def replayed_iteration(A, b, lam, off, tau, I):
+    """One iteration of Alg. 1 with the draws tau (3 blocks) and the greedy set
+    I given, from x0 = 0, by dense solves (numpy): the row-form update of
+    Lemma 2 for each step."""
+    x = np.zeros(A.shape[1])
+    for t in tau:
+        AS = A[off[t]:off[t + 1]]
+        r = b[off[t]:off[t + 1]] - AS @ x
+        x = x + AS.T @ np.linalg.solve(AS @ AS.T + lam * np.eye(len(r)), r)
+    AI = A[I]
+    r = b[I] - AI @ x
+    return x + AI.T @ np.linalg.solve(AI @ AI.T + lam * np.eye(len(I)), r)
+
+
+@pytest.mark.timeout(600)
+def test_paper_protocol_full_size():
+    """The paper's protocol on randn 60000 x 10000 (100 blocks of 600 rows):
+    S of every block, sampled stored inverses, one iteration with given draws
+    and greedy set against dense solves, and two free-running iterations
+    against the oracle."""
+    w = make("randn_60000x10000")
+    A, br, lam, seed = w["A"], w["block_rows"], w["lam"], w["seed"]
+    print("paper protocol: setup", flush=True)
+    sol = P.Solver(dev(A), br, lam)
+    assert sol.k == 100 and sol.K == 600 and not sol.column_form
+    check_setup(sol, A, br, lam, (0, 57, 99))
+    off = O.partition(A.shape[0], br)
+    rng = np.random.default_rng(3)
+    tau = np.array([5, 71, 5], dtype=np.int32)
+    I = np.sort(rng.choice(A.shape[0], 600, replace=False)).astype(np.int32)
+    sol.set_replay(tau, I[None, :], 1)
+    x, _ = sol.solve(dev(w["b"]), seed=0, tol=0.0, max_iters=1, replay=True)
+    e = rel(host(x), replayed_iteration(A, w["b"], lam, off, tau, I))
+    print(f"paper protocol: replayed iteration rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+    print("paper protocol: oracle", flush=True)
+    iters = 2
+    ref = O.solve(A, br, lam, w["b"], seed=seed, max_iters=iters)
+    x, _ = sol.solve(dev(w["b"]), seed=seed, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"paper protocol: {iters} iterations rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+
+
+@pytest.mark.timeout(300)
+def test_column_form_full_size():
+    """Blocks of 2000 rows against 500 columns (column form): S of every block,
+    sampled n x n stored inverses, and one iteration with given draws and
+    greedy set against dense row-form solves."""
+    w = make("colform_200000x500")
+    A, br, lam = w["A"], w["block_rows"], w["lam"]
+    print("column form full size: setup", flush=True)
+    sol = P.Solver(dev(A), br, lam)
+    assert sol.column_form and sol.K == 2000
+    np.testing.assert_allclose(sol.setup_arrays()["S"], O.cosine_rowsums(A, br), rtol=1e-12)
+    off = O.partition(A.shape[0], br)
+    for t in (0, 50, 99):
+        At = A[off[t]:off[t + 1]]
+        C = At.T @ At + lam * np.eye(A.shape[1])
+        assert rel(sol.block_inverse(t), np.linalg.inv(C)) < 50 * np.linalg.cond(C) * 2.2e-16
+    rng = np.random.default_rng(4)
+    tau = np.array([17, 3, 88], dtype=np.int32)
+    I = np.sort(rng.choice(A.shape[0], 2000, replace=False)).astype(np.int32)
+    b = w["b"] + 0.1 * rng.standard_normal(A.shape[0])
+    sol.set_replay(tau, I[None, :], 1)
+    x, _ = sol.solve(dev(b), seed=0, tol=0.0, max_iters=1, replay=True)
+    e = rel(host(x), replayed_iteration(A, b, lam, off, tau, I))
+    print(f"column form full size: replayed iteration rel err {e:.2e}", flush=True)
+    assert e < 1e-9
