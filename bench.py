@@ -10,8 +10,9 @@ the top-K greedy selection and the greedy block update.
 Other workloads (``--workload``): ``csr_200000`` (sparse square CSR, FP32
 values for the inner passes), ``wide_2000x50000``, ``dense_2000x200``; the
 paper's own protocol of 100 blocks (Section 3.1) on its dense random shapes,
-``randn_60000x10000`` (Table 3, blocks of 600 rows) and ``unif_100000x10000``
-(Table 5, blocks of 1000 rows), both to relative residual 1e-6; and
+``randn_60000x10000`` (Table 3, blocks of 600 rows) and ``unif_100000x10000``,
+``unif_100000x15000``, ``unif_100000x20000`` (Table 5, blocks of 1000 rows),
+all to relative residual 1e-6; and
 ``colform_200000x500`` (blocks of 2000 rows against 500 columns, solved in
 the column form).
 

@@ -160,6 +160,10 @@ WORKLOADS = {
                               block_rows=600, lam=None, tol=1e-6, max_iters=2000),
     "unif_100000x10000": dict(cfg=7, kind="unif1", m=100000, n=10000,
                               block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
+    "unif_100000x15000": dict(cfg=10, kind="unif1", m=100000, n=15000,
+                              block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
+    "unif_100000x20000": dict(cfg=9, kind="unif1", m=100000, n=20000,
+                              block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
     # tall and narrow with the paper's 100 blocks: blocks of 2000 rows against
     # 500 columns, the case for the column form of the block solve (Sec. 3.1)
     "colform_200000x500": dict(cfg=8, kind="dense", m=200000, n=500, cond=1e6,
