@@ -873,32 +873,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const double *__restrict__ Gpart, int nch, int K, double lambda,
     const double *__restrict__ rI, const double *__restrict__ Pin, int nchP, int bmax,
     double *__restrict__ y, Ctrl *__restrict__ ctrl) {
-    if (ctrl->done) return;
     constexpr int NTH = 256;
     __shared__ double Gp[64 * 65 / 2];
     __shared__ double z[64];
     __shared__ double colbuf[2 * MAXB];
     __shared__ double Lc[64 * 65];
+    // the stop flag is read by a vector load issued with the chunk loads (the
+    // Gram buffer is valid either way), so the two latencies overlap
+    const int stop = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int KP = K * (K + 1) / 2;
-    for (int f0 = 0; f0 < KP; f0 += NTH * 4) {
-        double g[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int c0 = 0; c0 < nch; c0 += 8) {
-            double t[4][8];
+    {
+        // every packed element of the 64 x 64 bound has its thread: the loads
+        // of eight chunks are in flight together, summed in chunk order (the
+        // addresses are clamped into the buffer and the extra values scaled
+        // by zero, so no load sits behind a branch)
+        constexpr int PER = (64 * 65 / 2 + NTH - 1) / NTH;
+        double g[PER];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < PER; ++u) g[u] = 0.0;
+        for (int c0 = 0; c0 < nch; c0 += 8) {
+            double t[PER][8];
+#pragma unroll
+            for (int u = 0; u < PER; ++u)
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const int f = f0 + threadIdx.x + u * NTH;
-                    t[u][c] = (f < KP && c0 + c < nch) ? Gpart[(int64_t)(c0 + c) * KP + f] : 0.0;
+                    const int f = threadIdx.x + u * NTH;
+                    const int fc = (f < KP) ? f : KP - 1;
+                    const int cc = (c0 + c < nch) ? c0 + c : nch - 1;
+                    const double keep = (f < KP && c0 + c < nch) ? 1.0 : 0.0;
+                    t[u][c] = Gpart[(int64_t)cc * KP + fc] * keep;
                 }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < PER; ++u)
 #pragma unroll
                 for (int c = 0; c < 8; ++c) g[u] += t[u][c];
         }
+        if (stop) return;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int f = f0 + threadIdx.x + u * NTH;
+        for (int u = 0; u < PER; ++u) {
+            const int f = threadIdx.x + u * NTH;
             if (f < KP) Gp[f] = g[u];
         }
     }

@@ -383,19 +383,34 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 // l_ik = g_ik / d_k, updates its row g_ij -= l_ik g_jk (j > k) with column k
 // read from LDS, and the forward substitution z_i -= l_ik z_k.  Column k+1 is
 // published to LDS right after its own update, so the write overlaps the rest
-// of the step.  The factor (l_ik below the diagonal, d_k on it) is kept column
-// by column in Lc[k * 65 + i] for the backward pass y_k = z_k / d_k -
-// sum_{i>k} l_ik y_i.  The steps are generated with compile-time k so that
-// every register index is static.
+// of the step.  1 / d_k is the hardware reciprocal r0 refined by Newton's
+// iteration, r1 = r0 (2 - d r0), with the second step folded into its uses
+// (l = g r1 + g r1 (1 - d r1)); the next pivot is formed straight from this
+// one, d_{k+1} = g_{k+1,k+1} - g_{k+1,k}^2 / d_k, so the chain from pivot to
+// pivot is two broadcasts and five dependent operations.  The factor (l_ik
+// below the diagonal, d_k on it) is kept column by column in Lc[k * 65 + i]
+// for the backward pass y_k = z_k / d_k - sum_{i>k} l_ik y_i.  The steps are
+// generated with compile-time k so that every register index is static.
 template <int k>
-__device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, int lane, double *colbuf,
-                                           double *Lc, bool &ok) {
+__device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, double &dnext, int lane,
+                                           double *colbuf, double *Lc, bool &ok) {
     const double *col = colbuf + (k & 1) * 64;
     double *nxt = colbuf + ((k + 1) & 1) * 64;
-    const double d = bcast64(a[k], k);
+    const double d = bcast64(dnext, k);
     ok = ok && (d > 0.0);
-    const double inv = 1.0 / d;
-    const double c = a[k] * inv;
+    const double r0 = __builtin_amdgcn_rcp(d);
+    const double e0 = __builtin_fma(-d, r0, 1.0);
+    const double r1 = __builtin_fma(r0, e0, r0);
+    const double e1 = __builtin_fma(-d, r1, 1.0);
+    const double akk = a[k];
+    const double m1 = akk * r1;
+    const double c = __builtin_fma(m1, e1, m1);
+    if constexpr (k + 1 < 64) {
+        const double t = akk * akk;
+        const double tr1 = t * r1;
+        const double u = __builtin_fma(-t, r1, a[k + 1]);
+        dnext = __builtin_fma(-tr1, e1, u);
+    }
     const double zk = bcast64(zi, k);
     zi = (lane > k) ? __builtin_fma(-c, zk, zi) : zi;
     Lc[k * 65 + lane] = (lane > k) ? c : d;
@@ -416,7 +431,8 @@ template <int... Ks>
 __device__ __forceinline__ void ldl_steps64(std::integer_sequence<int, Ks...>, double (&a)[64],
                                             double &zi, int lane, double *colbuf, double *Lc,
                                             bool &ok) {
-    (ldl_step64<Ks>(a, zi, lane, colbuf, Lc, ok), ...);
+    double dnext = a[0];
+    (ldl_step64<Ks>(a, zi, dnext, lane, colbuf, Lc, ok), ...);
 }
 
 // The system is padded to 64 x 64 with the identity beyond K (zero right-hand
