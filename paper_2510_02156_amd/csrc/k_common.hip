@@ -228,7 +228,8 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int shift, uint
 // Element i is taken by thread i % NT in round i / NT, so index order is
 // (round, wave, lane): ranks within a wave come from ballots, and the counts
 // of earlier (round, wave) pairs from one scan over their totals.  keys/ids
-// in LDS (ids == NULL: the position); outputs get base added.
+// in LDS (ids == NULL: the position); outputs get base added.  Rounds past
+// the last element (N <= ROUNDS * NT) are skipped by a uniform branch.
 template <int NT, int ROUNDS>
 __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, int K, uint64_t T,
                              uint64_t mask, int need, uint64_t *okey, int32_t *oidx,
@@ -239,11 +240,17 @@ __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, in
     // (each at most N <= 8192, so neither half carries into the other)
     __shared__ uint32_t wcnt[NS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nr = (N + NT - 1) / NT;   // rounds holding elements
     // per round: rank among the wave's "greater" lanes (bits 0..7), among its
     // "equal" lanes (bits 8..15), and the two flags (bits 16, 17)
     uint32_t rk[ROUNDS];
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
+        rk[u] = 0u;
+        if (u >= nr) {
+            if (lane == 0) wcnt[u * NW + w] = 0u;
+            continue;
+        }
         const int i = threadIdx.x + u * NT;
         const uint64_t mk = (i < N) ? (keys[i] & mask) : 0;
         const bool gt = (i < N) && mk > T, eq = (i < N) && mk == T;
@@ -271,16 +278,18 @@ __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, in
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
-        const int i = threadIdx.x + u * NT;
-        const uint32_t before = wcnt[u * NW + w];
-        const uint32_t g = (before >> 16) + (rk[u] & 0xffu);
-        const uint32_t q = (before & 0xffffu) + ((rk[u] >> 8) & 0xffu);
-        int pos = -1;
-        if (rk[u] & 0x10000u) pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
-        else if ((rk[u] & 0x20000u) && q < (uint32_t)need) pos = (int)(g + q);
-        if (pos >= 0 && pos < K) {
-            okey[pos] = keys[i];
-            oidx[pos] = (ids ? ids[i] : i) + base;
+        if (u < nr) {
+            const int i = threadIdx.x + u * NT;
+            const uint32_t before = wcnt[u * NW + w];
+            const uint32_t g = (before >> 16) + (rk[u] & 0xffu);
+            const uint32_t q = (before & 0xffffu) + ((rk[u] >> 8) & 0xffu);
+            int pos = -1;
+            if (rk[u] & 0x10000u) pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
+            else if ((rk[u] & 0x20000u) && q < (uint32_t)need) pos = (int)(g + q);
+            if (pos >= 0 && pos < K) {
+                okey[pos] = keys[i];
+                oidx[pos] = (ids ? ids[i] : i) + base;
+            }
         }
     }
     __syncthreads();
@@ -343,9 +352,15 @@ __device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *_
         for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
     }
     __syncthreads();
+    // ||r||^2 from the chunk norms: lane l of wave 0 sums chunks l, l + 64,
+    // ... in order, then a fixed butterfly over the lanes
+    double rn2 = 0.0;
+    if (threadIdx.x < 64) {
+        for (int c = threadIdx.x; c < ncn; c += 64) rn2 += (c < NCN) ? s_cn[c] : cn[c];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rn2 += __shfl_xor(rn2, off, 64);
+    }
     if (threadIdx.x == 0) {
-        double rn2 = 0.0;
-        for (int c = 0; c < ncn; ++c) rn2 += (c < NCN) ? s_cn[c] : cn[c];
         const double rn = sqrt(rn2);
         ctrl->rnorm2 = rn2;
         ctrl->last_it = it;
@@ -421,6 +436,7 @@ struct SelFinal {
 // LDS of the selection kernels: a chunk's keys, values and block norms, then
 // (fused form, last workgroup) the merge's keys, indices and chunk norms.
 constexpr int SEL_LDS = (SEL_MERGE * 8 + SEL_MERGE * 4 + (SEL_MERGE / 4) * 8) / 8;
+static_assert(2 * SEL_CHUNK + SEL_BPC <= SEL_LDS, "a chunk's keys, values and block norms fit");
 
 // Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
 // (Algorithm 1, the full residual), per-block ||r_t||^2, the chunk's ||r||^2,
@@ -504,10 +520,15 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // the chunk's ||r||^2: wave 0, lane l summing blocks l, l + 64, ... in
+    // order, then a fixed butterfly over the lanes
+    if (threadIdx.x < 64) {
+        const int nb = (int)(t1 - t0);
         double s = 0.0;
-        for (int64_t t = t0; t < t1; ++t) s += s_bn[t - t0];
-        cn[blockIdx.x] = s;
+        for (int g = threadIdx.x; g < nb; g += 64) s += s_bn[g];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) cn[blockIdx.x] = s;
     }
     if (do_topk) {
         uint64_t T, mask;
