@@ -332,8 +332,9 @@ __device__ void merge_lists(const uint64_t *__restrict__ ckey, const int32_t *__
 }
 
 // The end of an iteration's selection (one workgroup): the last candidate
-// merge (if do_topk), the RRN from the chunk norms in chunk order, the stop
-// test, the greedy set I (or the replayed one) with r_I, and the records.
+// merge (if do_topk), the RRN from the chunk norms (strided lane sums, then a
+// fixed butterfly), the stop test, the greedy set I (or the replayed one)
+// with r_I, and the records.
 // keys / ids / s_cn: LDS of SEL_MERGE, SEL_MERGE and SEL_MERGE / 4 entries.
 template <typename V>
 __device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
