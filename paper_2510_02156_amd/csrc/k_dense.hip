@@ -3,6 +3,7 @@
 // (centroid cosines, proposal, block inverses).  The residual pass is in
 // k_resid.hip.
 #include "rorbk_device.h"
+#include "gram_tiles.h"
 
 namespace rorbk {
 
@@ -542,6 +543,37 @@ __global__ __launch_bounds__(256) void k_block_gram_mfma(const T *__restrict__ A
     }
 }
 
+// The same block Grams on 64 x 64 tiles (gram_tiles.h) for blocks of at least
+// GRAM64_MIN_K rows: grid x = lower 64 x 64 tiles of the largest block, grid
+// y = blocks; each workgroup sums its tile over all n columns, with the
+// values of the 16 x 16 tile kernel.
+template <typename T, bool AL>
+__global__ __launch_bounds__(256) void k_block_gram64(const T *__restrict__ A, int64_t ld,
+                                                      int64_t n, int64_t q, int64_t rem,
+                                                      int64_t kpmax, double *__restrict__ Gs) {
+    const int64_t t = blockIdx.y;
+    const int bt = blk_rows(t, q, rem);
+    const int64_t r0 = blk_start(t, q, rem);
+    const int nt = (bt + 63) / 64;
+    int bi, bj;
+    tile_of(blockIdx.x, (int)((q + 1 + 63) / 64), &bi, &bj);
+    if (bi < 0 || bi >= nt || bj >= nt) return;   // uniform, before any barrier
+    const int li = threadIdx.x & 15;
+    const T *pa[4], *pb[4];
+    bool va[4], vb[4];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+        const int ia = bi * 64 + s2 * 16 + li, ib = bj * 64 + s2 * 16 + li;
+        va[s2] = ia < bt;
+        vb[s2] = ib < bt;
+        pa[s2] = A + (r0 + (va[s2] ? ia : 0)) * ld;
+        pb[s2] = A + (r0 + (vb[s2] ? ib : 0)) * ld;
+    }
+    dvec4 acc[4][4];
+    gram64_accumulate<T, AL>(pa, pb, va, vb, bi == bj, 0, n, acc);
+    gram64_store(acc, bi, bj, bt, Gs + t * kpmax);
+}
+
 // Stored inverse of each fixed block: (G_t + lambda I)^{-1} from the LDL^T
 // factor (LDS), column j by thread j (forward with unit L, scale by D^{-1},
 // backward with L^T), written row-major (the inverse is symmetric).
@@ -633,11 +665,18 @@ hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A, i
     double *Gs = nullptr;
     hipError_t e = hipMallocAsync((void **)&Gs, sizeof(double) * (size_t)(kp * L.k), s);
     if (e != hipSuccess) return e;
-    const int nt = (int)((L.bmax + 15) / 16);
+    const bool t64 = L.bmax >= GRAM64_MIN_K;
+    const int nt = (int)(t64 ? (L.bmax + 63) / 64 : (L.bmax + 15) / 16);
     dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)L.k);
 #define RORBK_BG(T)                                                                             \
     do {                                                                                        \
-        if (aligned)                                                                            \
+        if (t64 && aligned)                                                                     \
+            hipLaunchKernelGGL((k_block_gram64<T, true>), grid, dim3(256), 0, s,                \
+                               (const T *)A, L.ld, L.n, L.q, L.rem, kp, Gs);                    \
+        else if (t64)                                                                           \
+            hipLaunchKernelGGL((k_block_gram64<T, false>), grid, dim3(256), 0, s,               \
+                               (const T *)A, L.ld, L.n, L.q, L.rem, kp, Gs);                    \
+        else if (aligned)                                                                       \
             hipLaunchKernelGGL((k_block_gram_mfma<T, true>), grid, dim3(256), 0, s,             \
                                (const T *)A, L.ld, L.n, L.q, L.rem, kp, Gs);                    \
         else                                                                                    \

@@ -90,13 +90,36 @@ void plan_layout(Layout &L, bool col) {
         L.nseg = (int32_t)((n + 2047) / 2048);
     } else if (big) {
         // large blocks: one 128-column slab per update workgroup (row chunks
-        // add the rest of the parallelism); greedy Gram (32 x 32 tiles) chunks
-        // sized so that tiles x chunks is about 1024 workgroups
+        // add the rest of the parallelism).  Greedy Gram on 32 x 32 tiles:
+        // chunks sized so that tiles x chunks is about 1024 workgroups.  On
+        // 64 x 64 tiles (one workgroup per CU at a time) the chunk count c
+        // (up to 64, at least 256 columns each) minimises a time model in
+        // microseconds: rounds of 256 workgroups times one workgroup's MFMA
+        // time (n / c columns over 4 waves, 16 FP64 MFMAs of 64 cycles per 4
+        // columns, 2.4 GHz), plus writing and reading c packed partials at
+        // 5 TB/s
         L.wu = 128;
         L.nch_u = (int32_t)((n + 127) / 128);
-        const int64_t nt = (L.K + 31) / 32, tiles = nt * (nt + 1) / 2;
-        int64_t nch = (1024 + tiles - 1) / tiles;
-        if (nch > 64) nch = 64;
+        int64_t nch;
+        if (gram64_for(L.dtype, L.K)) {
+            const int64_t nt = (L.K + 63) / 64, tiles = nt * (nt + 1) / 2;
+            const double kp = 0.5 * (double)L.K * (double)(L.K + 1);
+            int64_t cap = n / 256;
+            if (cap > 64) cap = 64;
+            if (cap < 1) cap = 1;
+            nch = 1;
+            double best = 1e300;
+            for (int64_t c = 1; c <= cap; ++c) {
+                const double wg_us = (double)n / (double)c / 4.0 * 256.0 / 2400.0;
+                const double cost = (double)((tiles * c + 255) / 256) * wg_us +
+                                    (double)c * kp * 16.0 / 5.0e6;
+                if (cost < best * (1.0 - 1e-9)) { best = cost; nch = c; }
+            }
+        } else {
+            const int64_t nt = (L.K + 31) / 32, tiles = nt * (nt + 1) / 2;
+            nch = (1024 + tiles - 1) / tiles;
+            if (nch > 64) nch = 64;
+        }
         if (nch > (n + 31) / 32) nch = (n + 31) / 32;
         if (nch < 1) nch = 1;
         int64_t wg = (n + nch - 1) / nch;

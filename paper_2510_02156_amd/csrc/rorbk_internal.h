@@ -9,6 +9,14 @@
 
 namespace rorbk {
 
+// The greedy Gram of a large greedy set (dense, more than 161 rows) runs on
+// 64 x 64 tiles for FP64 storage with at least this many rows, else on
+// 32 x 32 tiles.
+constexpr int GRAM64_MIN_K = 256;
+__host__ __device__ constexpr bool gram64_for(int32_t dtype, int64_t K) {
+    return dtype == RORBK_F64 && K >= GRAM64_MIN_K;
+}
+
 // Device-resident control block.  Written only by the single-workgroup
 // selection and solve kernels; every iteration kernel reads `done` first and
 // returns at once when it is set (the stop test, Algorithm 1, ends the solve
