@@ -889,6 +889,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int q = tid; q < K; q += NTH) y[q] = yv[q];
 }
 
+// Packed Gram partials summed in chunk order into LDS, KP <= NU * 256: thread
+// t owns elements t + 256 u (u < NU) and keeps CG chunks of each in flight
+// together (about 72 loads).  Addresses are clamped into the buffer and the
+// extra values scaled by zero, so no load sits behind a branch.
+template <int NU>
+__device__ __forceinline__ void gram_sum_chunks(const double *__restrict__ Gpart, int nch, int KP,
+                                                double *__restrict__ Gp) {
+    constexpr int NTH = 256, CG = 8 * (9 / NU);
+    double g[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) g[u] = 0.0;
+    for (int c0 = 0; c0 < nch; c0 += CG) {
+        double t[NU][CG];
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int c = 0; c < CG; ++c) {
+                const int f = threadIdx.x + u * NTH;
+                const int fc = (f < KP) ? f : KP - 1;
+                const int cc = (c0 + c < nch) ? c0 + c : nch - 1;
+                const double keep = (f < KP && c0 + c < nch) ? 1.0 : 0.0;
+                t[u][c] = Gpart[(int64_t)cc * KP + fc] * keep;
+            }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+#pragma unroll
+            for (int c = 0; c < CG; ++c) g[u] += t[u][c];
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int f = threadIdx.x + u * NTH;
+        if (f < KP) Gp[f] = g[u];
+    }
+}
+
 // K <= 64: the whole solve on one wave (LDL^T in registers, ldl_wave64); the
 // blocked tile form above that.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_wave(
@@ -904,39 +939,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // Gram buffer is valid either way), so the two latencies overlap
     const int stop = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int KP = K * (K + 1) / 2;
-    {
-        // every packed element of the 64 x 64 bound has its thread: the loads
-        // of eight chunks are in flight together, summed in chunk order (the
-        // addresses are clamped into the buffer and the extra values scaled
-        // by zero, so no load sits behind a branch)
-        constexpr int PER = (64 * 65 / 2 + NTH - 1) / NTH;
-        double g[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) g[u] = 0.0;
-        for (int c0 = 0; c0 < nch; c0 += 8) {
-            double t[PER][8];
-#pragma unroll
-            for (int u = 0; u < PER; ++u)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int f = threadIdx.x + u * NTH;
-                    const int fc = (f < KP) ? f : KP - 1;
-                    const int cc = (c0 + c < nch) ? c0 + c : nch - 1;
-                    const double keep = (f < KP && c0 + c < nch) ? 1.0 : 0.0;
-                    t[u][c] = Gpart[(int64_t)cc * KP + fc] * keep;
-                }
-#pragma unroll
-            for (int u = 0; u < PER; ++u)
-#pragma unroll
-                for (int c = 0; c < 8; ++c) g[u] += t[u][c];
-        }
-        if (stop) return;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int f = threadIdx.x + u * NTH;
-            if (f < KP) Gp[f] = g[u];
-        }
+    // NU packed elements per thread, CG chunks of each in flight together
+    switch ((KP + NTH - 1) / NTH) {
+        case 1: gram_sum_chunks<1>(Gpart, nch, KP, Gp); break;
+        case 2: gram_sum_chunks<2>(Gpart, nch, KP, Gp); break;
+        case 3: gram_sum_chunks<3>(Gpart, nch, KP, Gp); break;
+        case 4: gram_sum_chunks<4>(Gpart, nch, KP, Gp); break;
+        case 5: gram_sum_chunks<5>(Gpart, nch, KP, Gp); break;
+        case 6: gram_sum_chunks<6>(Gpart, nch, KP, Gp); break;
+        case 7: gram_sum_chunks<7>(Gpart, nch, KP, Gp); break;
+        case 8: gram_sum_chunks<8>(Gpart, nch, KP, Gp); break;
+        default: gram_sum_chunks<9>(Gpart, nch, KP, Gp); break;
     }
+    if (stop) return;
     for (int q = threadIdx.x; q < K; q += NTH) {
         if (rI) {
             z[q] = rI[q];

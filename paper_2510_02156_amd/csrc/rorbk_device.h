@@ -391,9 +391,9 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 // below the diagonal, d_k on it) is kept column by column in Lc[k * 65 + i]
 // for the backward pass y_k = z_k / d_k - sum_{i>k} l_ik y_i.  The steps are
 // generated with compile-time k so that every register index is static.
-template <int k>
-__device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, double &dnext, int lane,
-                                           double *colbuf, double *Lc, bool &ok) {
+template <int N, int k>
+__device__ __forceinline__ void ldl_step(double (&a)[N], double &zi, double &dnext, int lane,
+                                         double *colbuf, double *Lc, bool &ok) {
     const double *col = colbuf + (k & 1) * 64;
     double *nxt = colbuf + ((k + 1) & 1) * 64;
     const double d = bcast64(dnext, k);
@@ -405,7 +405,7 @@ __device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, double &
     const double akk = a[k];
     const double m1 = akk * r1;
     const double c = __builtin_fma(m1, e1, m1);
-    if constexpr (k + 1 < 64) {
+    if constexpr (k + 1 < N) {
         const double t = akk * akk;
         const double tr1 = t * r1;
         const double u = __builtin_fma(-t, r1, a[k + 1]);
@@ -415,41 +415,43 @@ __device__ __forceinline__ void ldl_step64(double (&a)[64], double &zi, double &
     zi = (lane > k) ? __builtin_fma(-c, zk, zi) : zi;
     Lc[k * 65 + lane] = (lane > k) ? c : d;
     // column k (rows > k) into registers first, then the row update
-    double cv[64];
+    double cv[N];
 #pragma unroll
-    for (int j = k + 1; j < 64; ++j) cv[j] = col[j];
-    if constexpr (k + 1 < 64) {
+    for (int j = k + 1; j < N; ++j) cv[j] = col[j];
+    if constexpr (k + 1 < N) {
         a[k + 1] = __builtin_fma(-c, cv[k + 1], a[k + 1]);
         nxt[lane] = a[k + 1];
     }
 #pragma unroll
-    for (int j = k + 2; j < 64; ++j) a[j] = __builtin_fma(-c, cv[j], a[j]);
+    for (int j = k + 2; j < N; ++j) a[j] = __builtin_fma(-c, cv[j], a[j]);
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int... Ks>
-__device__ __forceinline__ void ldl_steps64(std::integer_sequence<int, Ks...>, double (&a)[64],
-                                            double &zi, int lane, double *colbuf, double *Lc,
-                                            bool &ok) {
+template <int N, int... Ks>
+__device__ __forceinline__ void ldl_steps(std::integer_sequence<int, Ks...>, double (&a)[N],
+                                          double &zi, int lane, double *colbuf, double *Lc,
+                                          bool &ok) {
     double dnext = a[0];
-    (ldl_step64<Ks>(a, zi, dnext, lane, colbuf, Lc, ok), ...);
+    (ldl_step<N, Ks>(a, zi, dnext, lane, colbuf, Lc, ok), ...);
 }
 
-// The system is padded to 64 x 64 with the identity beyond K (zero right-hand
-// side), which leaves the leading K x K factor and solution unchanged and keeps
-// the 64 unrolled steps free of branches.
-__device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
-                                  double *Lc /* 64*65 */) {
+// The system is padded to N x N (N = 32 or 64, K <= N) with the identity
+// beyond K (zero right-hand side), which leaves the leading K x K factor and
+// solution unchanged and keeps the N unrolled steps free of branches; lanes
+// from N on carry no row and their values are never used.
+template <int N>
+__device__ inline bool ldl_wave(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
+                                double *Lc /* 64*65 */) {
     const int lane = threadIdx.x & 63;
-    double a[64];
+    double a[N];
 #pragma unroll
-    for (int j = 0; j < 64; ++j)
+    for (int j = 0; j < N; ++j)
         a[j] = (lane < K && j < K) ? ((j <= lane) ? Gp[pk(lane, j)] : 0.0) : (j == lane ? 1.0 : 0.0);
     double zi = (lane < K) ? z[lane] : 0.0;
     colbuf[lane] = a[0];
     __builtin_amdgcn_wave_barrier();
     bool ok = true;
-    ldl_steps64(std::make_integer_sequence<int, 64>{}, a, zi, lane, colbuf, Lc, ok);
+    ldl_steps<N>(std::make_integer_sequence<int, N>{}, a, zi, lane, colbuf, Lc, ok);
     if (!ok) return false;
     // backward substitution, column oriented
     double w = zi / Lc[lane * 65 + lane];
@@ -460,6 +462,12 @@ __device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *co
     if (lane < K) z[lane] = w;
     __builtin_amdgcn_wave_barrier();
     return true;
+}
+
+// K <= 64 on one wave: the 32-row form when it suffices.
+__device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf,
+                                  double *Lc) {
+    return (K <= 32) ? ldl_wave<32>(Gp, z, K, colbuf, Lc) : ldl_wave<64>(Gp, z, K, colbuf, Lc);
 }
 
 }  // namespace rorbk
