@@ -633,261 +633,11 @@ hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream
 }
 
 // ------------------------------------------------------ greedy block solve --
-// (A_I A_I^T + lambda I) y = rhs, the greedy step of Algorithm 1.  For K > 64 a
-// blocked Cholesky factorisation on 16 x 16 tiles in one workgroup (4 waves):
-//  - the packed Gram partials of the column chunks are summed in chunk order
-//    into LDS (coalesced, loads in flight together) and lambda is added;
-//  - the matrix is augmented with rhs as row K, so the factor's last row is
-//    z = L^{-1} rhs (forward substitution comes out of the factorisation);
-//    rows past K pad the last tile with the identity;
-//  - lower tiles live in registers in the FP64 MFMA accumulator layout, tile
-//    f = I (I + 1) / 2 + J owned by wave f % 4.  For each tile column p: the
-//    diagonal tile is factored on one wave (rows in registers, readlane
-//    broadcasts), the tiles below are solved against it row by row (TRSM, one
-//    row per thread, in LDS), and every trailing tile takes
-//    -= L_{I,p} L_{J,p}^T with four v_mfma_f64_16x16x4f64 steps;
-//  - y = L^{-T} z by tile columns from the last: the products of the solved
-//    tiles are reduced in a fixed order (lane butterfly, waves in order), then
-//    a 16-step triangular solve on one wave.
-// rhs = r_I (forward) or, for the adjoint, -(sum of the partial products A_I g).
+// (A_I A_I^T + lambda I) y = rhs, the greedy step of Algorithm 1, rhs = r_I
+// (forward) or, for the adjoint, -(sum of the partial products A_I g).  Greedy
+// sets of at most 64 rows are solved by k_chol_wave below; larger ones by the
+// blocked Cholesky on 32 x 32 tiles (one launch per tile column, k_big.hip).
 // A pivot that is not positive (or not finite) sets RORBK_ERR_NOT_SPD.
-constexpr int CH_TMAX = (MAXB + 1 + 15) / 16;         // tiles per side (rhs row included)
-constexpr int CH_LDS = (PACKED_MAX > 2 * CH_TMAX * 16 * 17) ? PACKED_MAX : 2 * CH_TMAX * 16 * 17;
-
-__device__ __forceinline__ void tile_unpack(int f, int *I, int *J) {
-    int a = 0;
-    while ((a + 1) * (a + 2) / 2 <= f) ++a;
-    *I = a;
-    *J = f - a * (a + 1) / 2;
-}
-
-template <int MAXS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_mfma(
-    const double *__restrict__ Gpart, int nch, int K, double lambda,
-    const double *__restrict__ rI, const double *__restrict__ Pin, int nchP, int bmax,
-    double *__restrict__ y, Ctrl *__restrict__ ctrl) {
-    if (ctrl->done) return;
-    constexpr int NTH = 256;
-    __shared__ double lds[CH_LDS];          // packed Gram, then the panel and diagonal tiles
-    __shared__ double invD[CH_TMAX][16];    // 1 / L_kk of every diagonal tile
-    __shared__ double zv[CH_TMAX * 16], yv[CH_TMAX * 16];
-    __shared__ double red[4][16];
-    __shared__ int s_fail;
-    // the wave index is uniform across a wave: say so, so that every per-tile
-    // branch below is a scalar branch
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int N = K + 1, T = (N + 15) / 16, NT = T * (T + 1) / 2;
-    const int KP = K * (K + 1) / 2;
-    // 1. Gram partials summed in chunk order into LDS (each thread's elements
-    //    f = tid + u * NTH, 16 of them with all their chunk loads in flight);
-    //    rhs into zv
-    for (int f0 = 0; f0 < KP; f0 += NTH * 16) {
-        double g[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) g[u] = 0.0;
-        for (int c0 = 0; c0 < nch; c0 += 2) {
-            double t[16][2];
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int f = f0 + tid + u * NTH;
-                    t[u][c] = (f < KP && c0 + c < nch) ? Gpart[(int64_t)(c0 + c) * KP + f] : 0.0;
-                }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) g[u] += t[u][c];
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int f = f0 + tid + u * NTH;
-            if (f < KP) lds[f] = g[u];
-        }
-    }
-    for (int q = tid; q < T * 16; q += NTH) {
-        double v = 0.0;
-        if (q < K) {
-            if (rI) {
-                v = rI[q];
-            } else {
-                double sacc = 0.0;
-                for (int c = 0; c < nchP; ++c) sacc += Pin[(int64_t)c * bmax + q];
-                v = -sacc;
-            }
-        }
-        zv[q] = v;
-        yv[q] = 0.0;
-    }
-    if (tid == 0) s_fail = 0;
-    __syncthreads();
-    // 2. this wave's tiles of the augmented matrix, MFMA accumulator layout:
-    //    register r of lane l holds element (4 r + l / 16, l % 16) of the tile
-    dvec4 acc[MAXS];
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-        const int f = w + 4 * s;
-        acc[s] = (dvec4){0.0, 0.0, 0.0, 0.0};
-        if (f < NT) {
-            int I, J;
-            tile_unpack(f, &I, &J);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = I * 16 + 4 * r + (lane >> 4), j = J * 16 + (lane & 15);
-                double v;
-                if (i < K && j < K) v = (j <= i) ? lds[pk(i, j)] + (i == j ? lambda : 0.0) : 0.0;
-                else if (i == K && j < K) v = zv[j];
-                else v = (i == j) ? 1.0 : 0.0;
-                acc[s][r] = v;
-            }
-        }
-    }
-    __syncthreads();
-    double(*Pb)[16][17] = reinterpret_cast<double(*)[16][17]>(lds);                 // [T]
-    double(*Dg)[16][17] = reinterpret_cast<double(*)[16][17]>(lds + CH_TMAX * 16 * 17); // [T]
-    const int IK = K >> 4, iK = K & 15;   // tile row and row of the rhs
-    // 3. factorisation, tile column by tile column
-    for (int p = 0; p < T; ++p) {
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            const int f = w + 4 * s;
-            if (f < NT) {
-                int I, J;
-                tile_unpack(f, &I, &J);
-                if (J == p) {
-                    double(*dst)[17] = (I == p) ? Dg[p] : Pb[I];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dst[4 * r + (lane >> 4)][lane & 15] = acc[s][r];
-                }
-            }
-        }
-        __syncthreads();
-        if (w == 0) {
-            // diagonal tile: lane i < 16 holds row i; right-looking Cholesky
-            double a[16];
-            const int i = lane & 15;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) a[j] = Dg[p][i][j];
-            bool ok = true;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int gk = p * 16 + k;
-                double piv = bcast64(a[k], k);
-                if (gk < K) ok = ok && (piv > 0.0) && isfinite(piv);
-                else piv = 1.0;                 // rhs column and padding
-                const double lkk = sqrt(piv), inv = 1.0 / lkk;
-                if (i > k) a[k] *= inv;
-                if (i == k) a[k] = lkk;
-#pragma unroll
-                for (int j = k + 1; j < 16; ++j) {
-                    const double ljk = bcast64(a[k], j);
-                    if (i >= j) a[j] = __builtin_fma(-a[k], ljk, a[j]);
-                }
-                if (lane == 0) invD[p][k] = inv;
-            }
-            if (lane < 16) {
-#pragma unroll
-                for (int j = 0; j < 16; ++j) Dg[p][i][j] = a[j];
-                if (p == IK && i == iK)            // the rhs row inside this tile
-                    for (int j = 0; j < iK; ++j) zv[p * 16 + j] = a[j];
-            }
-            if (lane == 0 && !ok) s_fail = 1;
-        }
-        __syncthreads();
-        if (s_fail) {
-            if (tid == 0) {
-                ctrl->status = RORBK_ERR_NOT_SPD;
-                ctrl->done = 1;
-            }
-            return;
-        }
-        // tiles below the diagonal: row x of tile I solves x L_pp^T = a
-        const int below = (T - p - 1) * 16;
-        for (int rr = tid; rr < below; rr += NTH) {
-            const int I = p + 1 + (rr >> 4), i = rr & 15;
-            double x[16];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) x[k] = Pb[I][i][k];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                double sacc = x[k];
-#pragma unroll
-                for (int j = 0; j < k; ++j) sacc = __builtin_fma(-x[j], Dg[p][k][j], sacc);
-                x[k] = sacc * invD[p][k];
-            }
-#pragma unroll
-            for (int k = 0; k < 16; ++k) Pb[I][i][k] = x[k];
-            if (I == IK && i == iK)
-#pragma unroll
-                for (int k = 0; k < 16; ++k) zv[p * 16 + k] = x[k];
-        }
-        __syncthreads();
-        // solved tiles back to their owners; trailing updates on MFMA
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            const int f = w + 4 * s;
-            if (f < NT) {
-                int I, J;
-                tile_unpack(f, &I, &J);
-                if (J == p && I > p) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[s][r] = Pb[I][4 * r + (lane >> 4)][lane & 15];
-                } else if (J > p) {
-#pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) {
-                        const double av = -Pb[I][lane & 15][4 * ks + (lane >> 4)];
-                        const double bv = Pb[J][lane & 15][4 * ks + (lane >> 4)];
-                        acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[s], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // 4. y = L^{-T} z over rows 0..K-1, tile columns from the last
-    const int TK = (K + 15) / 16;
-    for (int p = TK - 1; p >= 0; --p) {
-        double part = 0.0;   // lane j (< 16 after the butterfly): this wave's sum for column j
-#pragma unroll
-        for (int s = 0; s < MAXS; ++s) {
-            const int f = w + 4 * s;
-            if (f < NT) {
-                int I, J;
-                tile_unpack(f, &I, &J);
-                if (J == p && I > p && I < TK) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = I * 16 + 4 * r + (lane >> 4);
-                        part = __builtin_fma(acc[s][r], yv[gi], part);   // yv = 0 past K
-                    }
-                }
-            }
-        }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (lane < 16) red[w][lane] = part;
-        __syncthreads();
-        if (w == 0) {
-            const int j = lane & 15;
-            double t = zv[p * 16 + j] - (((red[0][j] + red[1][j]) + red[2][j]) + red[3][j]);
-            double lcol[16];   // lane j: column j of L_pp, i.e. L_pp[k][j] for k > j
-#pragma unroll
-            for (int k = 0; k < 16; ++k) lcol[k] = Dg[p][k][j];
-            double yk_all = 0.0;
-#pragma unroll
-            for (int k = 15; k >= 0; --k) {
-                const int gk = p * 16 + k;
-                const double yk = (gk < K) ? bcast64(t, k) * invD[p][k] : 0.0;
-                if (j == k) yk_all = yk;
-                if (j < k) t = __builtin_fma(-lcol[k], yk, t);
-            }
-            if (lane < 16) yv[p * 16 + j] = yk_all;
-        }
-        __syncthreads();
-    }
-    for (int q = tid; q < K; q += NTH) y[q] = yv[q];
-}
 
 // Packed Gram partials summed in chunk order into LDS, KP <= NU * 256: thread
 // t owns elements t + 256 u (u < NU) and keeps CG chunks of each in flight
@@ -924,8 +674,7 @@ __device__ __forceinline__ void gram_sum_chunks(const double *__restrict__ Gpart
     }
 }
 
-// K <= 64: the whole solve on one wave (LDL^T in registers, ldl_wave64); the
-// blocked tile form above that.
+// K <= 64: the whole solve on one wave (LDL^T in registers, ldl_wave64).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_wave(
     const double *__restrict__ Gpart, int nch, int K, double lambda,
     const double *__restrict__ rI, const double *__restrict__ Pin, int nchP, int bmax,
@@ -979,20 +728,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                              const double *rI, const double *Pin, double *y, hipStream_t s) {
     const Layout &L = h->L;
-    if (K > MAXB) return launch_big_chol_solve(h, Gpart, K, rI, Pin, y, s);
-    if (K <= 64) {
-        hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K, h->lambda,
-                           rI, Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
-        return hipGetLastError();
+    if (K > 64) {
+        // the handle holds the blocked factorisation's buffers for every
+        // greedy set of more than 64 rows
+        if (!h->d_bigG) return hipErrorInvalidValue;
+        return launch_big_chol_solve(h, Gpart, K, rI, Pin, y, s);
     }
-    const int T = (K + 1 + 15) / 16, NT = T * (T + 1) / 2, slots = (NT + 3) / 4;
-#define RORBK_CH(S)                                                                         \
-    hipLaunchKernelGGL((k_chol_mfma<S>), dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K,       \
-                       h->lambda, rI, Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl)
-    if (slots <= 8) RORBK_CH(8);
-    else if (slots <= 12) RORBK_CH(12);
-    else RORBK_CH(17);
-#undef RORBK_CH
+    hipLaunchKernelGGL(k_chol_wave, dim3(1), dim3(256), 0, s, Gpart, L.nch_g, K, h->lambda, rI,
+                       Pin, L.nch_u, (int)L.bmax, y, h->d_ctrl);
     return hipGetLastError();
 }
 

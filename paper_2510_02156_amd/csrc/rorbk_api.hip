@@ -604,11 +604,15 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_selcnt, 1);
     ALLOC(h->d_ysum, L.n);
     ALLOC(h->d_alg2, 3);
-    if (h->big) {
+    if (h->big || gdim > 64) {
+        // the blocked Cholesky of the greedy system (every greedy set of more
+        // than 64 rows)
         const int64_t P = (gdim + 31) / 32;
         ALLOC(h->d_bigG, (P + 1) * 32 * P * 32);
         ALLOC(h->d_bigL, (P + 1) * 32 * P * 32);
         ALLOC(h->d_bigW, P * 32 * 32);
+    }
+    if (h->big) {
         ALLOC(h->d_bigr, bmax);
         ALLOC(h->d_bigy, bmax);
         char *p1 = nullptr, *p2 = nullptr;
