@@ -42,11 +42,19 @@ struct StepP {
 
 constexpr int STEP_T = 512;  // threads of the block step
 
+// Workgroup barrier that orders LDS only: global loads issued before it stay
+// in flight across it (used where the barrier protects LDS data alone).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // row groups of the block step for storage T (8 for FP64, 16 FP32, 32 BF16)
 template <typename T>
 constexpr int step_groups() { return STEP_T / (128 / Tr<T>::VW); }
 
-template <typename T, typename V, bool AL, int RPT>
+template <typename T, typename V, bool AL, int RPT, bool MS>
 __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
     constexpr int VW = Tr<T>::VW;
     constexpr int NV = 128 / VW;       // lanes across a slab
@@ -180,9 +188,26 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
     V pacc[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) pacc[r] = (V)0;
+    // 128-column sub-slabs in turn.  With several sub-slabs per workgroup
+    // (MS) and up to 9 rows per thread the next sub-slab's rows are loaded
+    // while this one is reduced (its barriers order LDS only, so the loads
+    // stay in flight); otherwise each sub-slab loads its own rows
+    constexpr bool PF = MS && RPT <= 9;
+    constexpr int RP = PF ? RPT : 1;
     for (int64_t sub = c0; sub < c1; sub += 128) {
         const int64_t col = sub + (int64_t)v * VW;
-        if (sub != c0) {
+        const bool more = sub + 128 < c1;   // uniform
+        uvec4 ua2[RP], un2[RP];
+        if constexpr (PF) {
+            if (more) {
+                const int64_t coln = col + 128;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    ua2[r] = (crow[r] >= 0 && coln < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, coln, c1) : zero4;
+                    un2[r] = (nrow[r] >= 0 && coln < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, coln, c1) : zero4;
+                }
+            }
+        } else if (sub != c0) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 ua[r] = (crow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, col, c1) : zero4;
@@ -202,7 +227,8 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
             }
 #pragma unroll
             for (int e = 0; e < VW; ++e) s_red[g][v * VW + e] = acc[e];
-            __syncthreads();
+            if (PF) lds_barrier();
+            else __syncthreads();
             if (tid < 128) {
                 const int64_t cc = sub + tid;
                 if (cc < c1) {
@@ -211,7 +237,8 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
                     s_x[cc - c0] += s;
                 }
             }
-            __syncthreads();
+            if (PF) lds_barrier();
+            else __syncthreads();
         }
         if (col < c1) {
 #pragma unroll
@@ -221,6 +248,15 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
 #pragma unroll
                 for (int e = 0; e < VW; ++e)
                     if (col + e < c1) pacc[r] = fmaT(a[e], s_x[col + e - c0], pacc[r]);
+            }
+        }
+        if constexpr (PF) {
+            if (more) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    ua[r] = ua2[r];
+                    un[r] = un2[r];
+                }
             }
         }
     }
@@ -284,19 +320,25 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const T *__restrict__ A, int6
 }
 
 // ------------------------------------------------------------ launchers --
+template <typename T, typename V, bool AL, bool MS>
+static hipError_t step_launch_ms(const StepP &p, int nblk, int rpt, hipStream_t s) {
+    if (rpt <= 3)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 3, MS>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else if (rpt <= 5)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 5, MS>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else if (rpt <= 9)
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 9, MS>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_step_dense<T, V, AL, 21, MS>), dim3(nblk), dim3(STEP_T), 0, s, p);
+    return hipGetLastError();
+}
+
 template <typename T, typename V, bool AL>
 static hipError_t step_launch_rpt(const StepP &p, int nblk, int bmax, hipStream_t s) {
     constexpr int G = step_groups<T>();
     const int rpt = (bmax + G - 1) / G;
-    if (rpt <= 3)
-        hipLaunchKernelGGL((k_step_dense<T, V, AL, 3>), dim3(nblk), dim3(STEP_T), 0, s, p);
-    else if (rpt <= 5)
-        hipLaunchKernelGGL((k_step_dense<T, V, AL, 5>), dim3(nblk), dim3(STEP_T), 0, s, p);
-    else if (rpt <= 9)
-        hipLaunchKernelGGL((k_step_dense<T, V, AL, 9>), dim3(nblk), dim3(STEP_T), 0, s, p);
-    else
-        hipLaunchKernelGGL((k_step_dense<T, V, AL, 21>), dim3(nblk), dim3(STEP_T), 0, s, p);
-    return hipGetLastError();
+    if (p.wu > 128) return step_launch_ms<T, V, AL, true>(p, nblk, rpt, s);
+    return step_launch_ms<T, V, AL, false>(p, nblk, rpt, s);
 }
 
 template <typename T, typename V>
