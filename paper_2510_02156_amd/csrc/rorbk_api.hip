@@ -128,8 +128,16 @@ void plan_layout(Layout &L, bool col) {
         L.nch_g = (int32_t)((n + wg - 1) / wg);
         L.nseg = (int32_t)((n + 2047) / 2048);
     } else if (L.format == RORBK_DENSE) {
+        // 128-column slabs per update workgroup: one up to 64 slabs, then two
+        // (the next slab's rows load while one is reduced) or more, so that
+        // there are at most about 256 workgroups whose partial products the
+        // next step sums; at most 8 (x stays in LDS)
         const int64_t slabs = (n + 127) / 128;
-        int64_t per = (slabs + 63) / 64;  // slabs per workgroup (<= 8 keeps x in LDS)
+        int64_t per = 1;
+        if (slabs > 64) {
+            per = (slabs + 255) / 256;
+            if (per < 2) per = 2;
+        }
         if (per > 8) per = 8;
         L.wu = 128 * per;
         L.nch_u = (int32_t)((n + L.wu - 1) / L.wu);
