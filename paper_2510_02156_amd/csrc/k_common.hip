@@ -332,7 +332,7 @@ __device__ void merge_lists(const uint64_t *__restrict__ ckey, const int32_t *__
 }
 
 // The end of an iteration's selection (one workgroup): the last candidate
-// merge (if do_topk), the RRN from the chunk norms (strided lane sums, then a
+// merge (if do_topk and there is more than one list), the RRN from the chunk norms (strided lane sums, then a
 // fixed butterfly), the stop test, the greedy set I (or the replayed one)
 // with r_I, and the records.
 // keys / ids / s_cn: LDS of SEL_MERGE, SEL_MERGE and SEL_MERGE / 4 entries.
@@ -348,9 +348,12 @@ __device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *_
     __shared__ int32_t fi[MAXK];
     constexpr int NCN = SEL_MERGE / 4;
     for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
-    if (do_topk) {
+    if (do_topk && nlists > 1) {
         merge_lists<V>(ckey, cidx, nlists * K, K, keys, ids, fk, fi);
         for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
+    } else if (do_topk) {
+        // one chunk: its list (ascending rows) is the top K
+        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = cidx[p];
     }
     __syncthreads();
     // ||r||^2 from the chunk norms: lane l of wave 0 sums chunks l, l + 64,
