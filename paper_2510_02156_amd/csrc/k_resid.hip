@@ -10,7 +10,7 @@ constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 // ------------------------------------------------------------ residual pass --
 // Algorithm 1, r = b - A x: the products (A x)_i over one 2048-column segment
 // (SW columns of it when the whole matrix is narrower, SW = 512 or 1024).
-// A persistent grid (two workgroups per CU) walks the rows: wave w takes rows
+// A grid of a few workgroups per CU walks the rows: wave w takes rows
 // w*ROWS .. w*ROWS+ROWS-1, then the same rows plus nwaves*ROWS, and so on.
 // For each group of ROWS rows every 16-byte load of the group is issued
 // (non-temporal, raw bytes) before any of them is converted or used, so each
@@ -74,11 +74,21 @@ static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligne
                               const void *x, double *axp, hipStream_t s) {
     static_assert(SW == SEG || SW == 512 || SW == 1024, "segment width");
     const Layout &L = h->L;
-    // persistent grid: 2 workgroups (8 waves) per CU over all segments, fewer
-    // for short matrices; with many segments (wide matrices) each wave keeps
-    // its slice of x for many rows
+    // grid over all segments: 16 workgroups per CU for FP32 and FP64 rows of
+    // full 2048-column segments (more than are resident at once: the later
+    // ones fill in as the first finish, which evens out the tail), as long as
+    // every wave still takes at least 3 row groups (each wave loads its slice
+    // of x once); 2 per CU otherwise (BF16 and narrow rows are slower with
+    // more); fewer for short matrices
+    constexpr int PER_CU = (SW == SEG && sizeof(T) >= 4) ? 16 : 2;
     int64_t groups = (L.m + 4 * ROWS - 1) / (4 * ROWS);
-    int64_t cap = 2 * (int64_t)h->ncu / L.nseg;
+    int64_t cap = PER_CU * (int64_t)h->ncu / L.nseg;
+    if (PER_CU > 2) {
+        int64_t c3 = L.m / (4 * ROWS * 3);
+        const int64_t c2 = 2 * (int64_t)h->ncu / L.nseg;
+        if (c3 < c2) c3 = c2;
+        if (cap > c3) cap = c3;
+    }
     if (cap < 1) cap = 1;
     if (groups > cap) groups = cap;
     dim3 grid((unsigned)groups, (unsigned)L.nseg);
