@@ -1,7 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the
 benchmark times: the tall dense 100000 x 2000 system (FP64 and FP32 storage),
-the wide 2000 x 50000 system, and the 2000 x 200 system over the whole
-5000-iteration cap.  Outputs the oracle computes one by one (S of every
+the wide 2000 x 50000 system, the 2000 x 200 system over the whole
+5000-iteration cap, and the paper's 100-block protocol on its randn 60000 x
+10000 and 1 + U(0,1) 100000 x 20000 shapes and on the column form.  Outputs
+the oracle computes one by one (S of every
 block, sampled block inverses, a few iterations) are compared directly; the
 wide case also checks Lemma 2's range-space property, which holds at any size.
 """
@@ -182,3 +184,26 @@ def test_column_form_full_size():
     e = rel(host(x), replayed_iteration(A, b, lam, off, tau, I))
     print(f"column form full size: replayed iteration rel err {e:.2e}", flush=True)
     assert e < 1e-9
+
+
+@pytest.mark.timeout(600)
+def test_table5_full_size():
+    """The largest Table 5 shape, 100000 x 20000 with entries 1 + U(0,1) and
+    100 blocks of 1000 rows (FP64 storage: the setup's block Grams and the
+    greedy Gram run on 64 x 64 tiles): S of every block, two stored inverses,
+    and one iteration with given draws and greedy set against dense solves."""
+    w = make("unif_100000x20000")
+    A, br, lam = w["A"], w["block_rows"], w["lam"]
+    print("table 5 full size: setup", flush=True)
+    sol = P.Solver(dev(A), br, lam)
+    assert sol.k == 100 and sol.K == 1000 and not sol.column_form
+    check_setup(sol, A, br, lam, (0, 99))
+    off = O.partition(A.shape[0], br)
+    rng = np.random.default_rng(6)
+    tau = np.array([42, 7, 42], dtype=np.int32)
+    I = np.sort(rng.choice(A.shape[0], 1000, replace=False)).astype(np.int32)
+    sol.set_replay(tau, I[None, :], 1)
+    x, _ = sol.solve(dev(w["b"]), seed=0, tol=0.0, max_iters=1, replay=True)
+    e = rel(host(x), replayed_iteration(A, w["b"], lam, off, tau, I))
+    print(f"table 5 full size: replayed iteration rel err {e:.2e}", flush=True)
+    assert e < 1e-10
