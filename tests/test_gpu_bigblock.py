@@ -28,6 +28,7 @@ CASES = [
     (1200, 700, 170, 1.7e-4, "svd"),      # 7 blocks of 172/171 rows: 6 tiles, ragged
     (2011, 900, 400, 4e-4, "randn"),      # 5 blocks of 403/402 rows: 13 tiles
     (1500, 2200, 300, 3e-4, "unif1"),     # wide, 5 blocks of 300 rows
+    (1300, 901, 320, 3.2e-4, "unif1"),    # odd n: FP64 rows not 16-byte aligned
 ]
 
 
