@@ -151,6 +151,43 @@ def test_free_running_matches_oracle(m, n, br, lam, cond):
     assert rel(host(x), ref["x"]) < 1e-10
 
 
+@pytest.mark.parametrize("m,n,br", [(400, 9001, 16), (420, 8960, 20)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_multi_slab_update_workgroups(m, n, br, storage):
+    """More than 64 slabs of 128 columns: each update workgroup takes two and
+    loads the second while the first is reduced (ragged last slab; odd n also
+    misaligns the FP64 rows).  FP64 storage against the oracle; FP32 storage
+    replayed on the oracle's draws and greedy sets against the oracle run on
+    the FP32-rounded matrix."""
+    s = make(m, n, 1e3)
+    lam = 1e-4
+    iters = 20
+    if storage == "f64":
+        A = s["A"]
+        ref = O.solve(A, br, lam, s["b"], seed=31, max_iters=iters)
+        sol = P.Solver(dev(A), br, lam)
+        _, Wref = O.proposal(O.cosine_rowsums(A, br), n)
+        sol.set_proposal(Wref)
+        x, _ = sol.solve(dev(s["b"]), seed=31, tol=0.0, max_iters=iters, record=True)
+        rec = sol.record()
+        np.testing.assert_array_equal(rec["tau"], ref["tau"])
+        np.testing.assert_array_equal(rec["I"], ref["I"])
+        e = rel(host(x), ref["x"])
+        print(f"multi-slab f64 m={m} n={n}: rel err {e:.2e}", flush=True)
+        assert e < 1e-10
+    else:
+        Av = s["A"].astype(np.float32).astype(np.float64)
+        b = Av @ s["xstar"]
+        ref = O.solve(Av, br, lam, b, seed=31, max_iters=iters)
+        sol = P.Solver(dev(s["A"], torch.float32), br, lam)
+        sol.set_replay(ref["tau"], ref["I"], iters)
+        x, _ = sol.solve(dev(b, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
+        assert x.dtype == torch.float32
+        e = rel(host(x), ref["x"])
+        print(f"multi-slab f32 m={m} n={n}: rel err vs FP64 oracle {e:.2e}", flush=True)
+        assert e < 1e-4
+
+
 def test_stop_test_and_iteration_count():
     s = make(1000, 300, 1e4)
     ref = O.solve(s["A"], 20, 1e-3, s["b"], seed=9, tol=0.05, max_iters=500)
