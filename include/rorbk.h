@@ -81,12 +81,21 @@ typedef struct rorbk_matrix {
 } rorbk_matrix;
 
 /* --------------------------------------------------------------- solve info */
+/* rrn is ||b - A x|| / ||b|| of the x the call returns, on every path: a
+ * converged plain solve returns the iterate whose residual passed the stop
+ * test (Algorithm 1 tests before the greedy step); a plain solve that ends at
+ * max_iters made one greedy update after its last test, so one more residual
+ * pass measures the returned x (in the solve's vector precision); REFINE
+ * measures it in FP64 with the master copy.  rrn_test is the last stop test
+ * of Algorithm 1 itself (the RRN history of ror_bk_get_record ends with it). */
 typedef struct rorbk_info {
     int64_t iters;       /* outer iterations run (inner ones under REFINE)   */
-    double rrn;          /* last measured ||b - A x|| / ||b||                 */
-    int32_t converged;   /* 1 if rrn < tol was reached                         */
+    double rrn;          /* ||b - A x|| / ||b|| of the returned x             */
+    int32_t converged;   /* 1 if the stop test ||r|| < tol ||b|| passed      */
     int32_t n_refine;    /* REFINE: outer FP64 correction steps               */
     double t_solve_s;    /* device time of the solve (HIP events)             */
+    double t_setup_s;    /* wall time of the handle's ror_bk_setup call (s)   */
+    double rrn_test;     /* RRN of the last stop test taken                   */
 } rorbk_info;
 
 typedef struct rorbk_handle_s *rorbk_handle;
@@ -100,6 +109,16 @@ typedef struct rorbk_handle_s *rorbk_handle;
 #define RORBK_PROFILE 16u    /* time the residual-pass kernel with HIP events
                                 (one launch in every 16 iterations, plus every
                                 FP64 outer pass); read with ror_bk_get_profile */
+
+/* Block partition (Algorithm 1, first step; Section 2: k blocks of at least
+ * floor(m/k) rows each), on the host, without a handle or any device work:
+ * k = floor(m / block_rows) contiguous blocks; the first m mod k of them take
+ * floor(m/k) + 1 rows, the others floor(m/k).  *k receives the block count;
+ * offsets_host (host, caller-owned, may be NULL to query k) receives the k+1
+ * row offsets, offsets_host[0] = 0 and offsets_host[k] = m, identical to the
+ * partition ror_bk_setup builds on the device.  RORBK_ERR_INVALID_ARG unless
+ * m >= 1 and 1 <= block_rows <= m (and k != NULL). */
+int ror_bk_partition(int64_t m, int64_t block_rows, int64_t *offsets_host, int64_t *k);
 
 /* Setup (Algorithm 1, first four steps; Section 3.1 for the stored block
  * inverses).  Partitions A into k = floor(m / block_rows) contiguous blocks of
@@ -139,21 +158,32 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed,
 int ror_bk_backward(rorbk_handle h, const void *grad_x, void *grad_b,
                     void *grad_x0);
 
-/* Release every device buffer of the handle (h may be NULL). */
+/* Release every device buffer the handle owns (the stored block inverses of
+ * Section 3.1, the proposal, workspaces and records); h may be NULL.  The
+ * caller's matrix and vectors are not touched. */
 int ror_bk_destroy(rorbk_handle h);
 
 /* ------------------------------------------------- inspection and replay -- */
 
-/* Sizes chosen by setup: k blocks, K greedy rows, largest block rows. */
+/* Sizes chosen by setup (Algorithm 1: k blocks from the first step; the
+ * greedy step's floor(m/k) rows): k, K = floor(m/k), and the largest block's
+ * rows.  Any pointer may be NULL (host, caller-owned). */
 int ror_bk_get_sizes(rorbk_handle h, int64_t *k, int64_t *K, int64_t *bmax);
 
-/* Copies of the setup results: offsets (k+1 int64), S, Pbar, W (k doubles
- * each).  Any pointer may be NULL. */
+/* Copies of the setup results of Algorithm 1's first four steps into host
+ * memory (caller-owned): the block offsets (k+1 int64, the partition), the
+ * cosine row sums S_t = sum_j |<c_t,c_j>| / (|c_t| |c_j|) over the centroids
+ * c_t (sums of the block's rows), Pbar_t = exp(-2 S_t / n) and the running
+ * sums W_t = Pbar_0 + ... + Pbar_t the sampler inverts (k doubles each).  Any
+ * pointer may be NULL.  Synchronises the stream. */
 int ror_bk_get_setup(rorbk_handle h, int64_t *offsets_host, double *S_host,
                      double *pbar_host, double *W_host);
 
-/* Replace the sampler's running sums W (k doubles, host), e.g. with another
- * implementation's table so that sampled indices can be compared bit for bit. */
+/* Replace the sampler's running sums W of the proposal (Algorithm 1, steps
+ * 3-4: W_t = Pbar_0 + ... + Pbar_t; Section 2, sampling by the proposal):
+ * W_host holds k doubles (host, copied), finite, non-negative and
+ * non-decreasing, else RORBK_ERR_INVALID_ARG.  Lets another implementation's
+ * table drive the draws, so that sampled indices can be compared bit for bit. */
 int ror_bk_set_proposal(rorbk_handle h, const double *W_host);
 
 /* Which form of the regularised block solve setup chose (Sec. 3.1): 0 for the
@@ -164,39 +194,61 @@ int ror_bk_set_proposal(rorbk_handle h, const double *W_host);
  * (Lemma 1), and ror_bk_backward differentiates either. */
 int ror_bk_get_form(rorbk_handle h, int32_t *column_form);
 
-/* The stored inverse of block t into host memory, row-major doubles: row
- * form (A_t A_t^T + lambda I)^{-1}, b_t x b_t; column form
- * (A_t^T A_t + lambda I)^{-1}, n x n. */
+/* The stored inverse of block t (Section 3.1 keeps the inverse of every
+ * fixed block's regularised Gram, so a sampled step costs O(nb)) into
+ * Hinv_host (host, caller-owned), row-major doubles: row form
+ * (A_t A_t^T + lambda I)^{-1}, b_t x b_t; column form
+ * (A_t^T A_t + lambda I)^{-1}, n x n.  RORBK_ERR_INVALID_ARG if t is outside
+ * [0, k).  Synchronises the stream. */
 int ror_bk_get_block_inverse(rorbk_handle h, int64_t t, double *Hinv_host);
 
-/* The block indices the sampler draws for iterations j0 .. j0+count-1
- * (3 per iteration, draw l of iteration j at [3(j-j0) + l - 1]), computed on
- * the device, copied to tau_host (3*count int32). */
+/* The sampled blocks of Algorithm 1's inner loop (three draws with
+ * replacement per outer iteration, from the proposal P = Pbar / sum Pbar of
+ * Section 2) for iterations j0 .. j0+count-1: draw l of iteration j uses word
+ * 3j + l - 1 of the counter-based SplitMix64 stream keyed by seed and inverts
+ * the running sums W (tau = number of W_t <= u W_{k-1}, at most k-1), at
+ * [3(j-j0) + l - 1] of tau_host (host, caller-owned, 3*count int32).  Computed
+ * on the device (a temporary buffer is allocated) and synchronised.
+ * RORBK_ERR_INVALID_ARG if count < 0 or j0 < 0. */
 int ror_bk_sample(rorbk_handle h, uint64_t seed, int64_t j0, int64_t count,
                   int32_t *tau_host);
 
-/* The greedy selection on a given residual: the K indices of largest |r_i|
- * (ties to the lower index), ascending.  r: device, m entries of the solve's
- * vector type (vec_f32 = 0: double, 1: float).  idx: device, K int32. */
+/* The greedy step's selection of Algorithm 1 (the floor(m/k) rows of largest
+ * r_i^2, the paragraph after the listing) on a given vector: the K indices of
+ * largest |r_i| (ties to the lower index), ascending.  r: device, m entries
+ * of the solve's vector type (vec_f32 = 0: double, 1: float), caller-owned,
+ * read only.  idx: device, K int32, written.  Synchronises the stream;
+ * RORBK_ERR_NONFINITE if r holds a NaN or Inf. */
 int ror_bk_topk(rorbk_handle h, const void *r, int32_t vec_f32, int32_t *idx);
 
-/* One residual pass r = b - A x with the per-block squared norms
- * ||r_t||^2 (block_norm2, device, k doubles) and ||r|| / ||b|| in *rrn_host.
- * b, x, r: device, of the vector type given by vec_f32 (0: double; 1: float,
- * only for F32/BF16 storage).  use_f64_master = 1 reads the FP64 master copy. */
+/* One full residual pass of Algorithm 1 (r = b - A x, the step before the
+ * stop test; its O(mn) cost per iteration is the one Section 3.1 names) with
+ * the per-block squared norms ||r_t||^2 (block_norm2, device, k doubles, may
+ * be NULL) and ||r|| / ||b|| in *rrn_host (host, may be NULL).  b, x: device,
+ * read; r: device, written; all of the vector type given by vec_f32 (0:
+ * double; 1: float, only for F32/BF16 storage).  use_f64_master = 1 reads the
+ * FP64 master copy (double vectors).  Synchronises the stream;
+ * RORBK_ERR_NONFINITE if the residual holds a NaN or Inf. */
 int ror_bk_residual(rorbk_handle h, const void *b, const void *x, void *r,
                     double *block_norm2, int32_t vec_f32,
                     int32_t use_f64_master, double *rrn_host);
 
-/* Selections of the last RECORD (or CHECKPOINT-recomputed) solve: tau
- * (3*iters int32), greedy sets (iters*K int32), RRN history (iters doubles),
- * each pointer may be NULL; *iters_host receives the iterations recorded. */
+/* What the last solve on the handle recorded of Algorithm 1 (host buffers,
+ * caller-owned, each may be NULL): tau (3*iters int32, the inner loop's
+ * sampled blocks), the greedy sets I (iters*K int32, rows ascending; only
+ * when the last solve ran with RECORD or CHECKPOINT, else
+ * RORBK_ERR_NOT_RECORDED), and the history of the stop test's
+ * RRN (iters doubles); *iters_host receives the iteration count.  A later
+ * solve (of any kind) replaces the record.  Synchronises the stream. */
 int ror_bk_get_record(rorbk_handle h, int32_t *tau_host, int32_t *I_host,
                       double *rrn_host, int64_t *iters_host);
 
-/* Selections for a RORBK_REPLAY solve of up to `iters` iterations: tau
- * (3*iters int32, block indices in [0,k)), greedy sets (iters*K int32, row
- * indices in [0,m), ascending within a set), host memory, copied. */
+/* The selections Algorithm 1 would otherwise make (the inner loop's three
+ * sampled blocks and the greedy step's rows) for RORBK_REPLAY solves of up to
+ * `iters` iterations: tau (3*iters int32, block indices in [0,k)), greedy sets
+ * (iters*K int32, row indices in [0,m), strictly ascending within a set),
+ * host memory, copied to the handle (device buffers allocated here).
+ * RORBK_ERR_INVALID_ARG on an index out of range or a set out of order. */
 int ror_bk_set_replay(rorbk_handle h, const int32_t *tau_host,
                       const int32_t *I_host, int64_t iters);
 
@@ -227,21 +279,27 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
 int ror_bk_initial_solution(rorbk_handle h, const void *b, void *x0, int32_t vec_f32,
                             double *coef_host);
 
-/* Refinement controls for RORBK_REFINE: inner iterations per FP64 correction
- * (default 50) and the inner relative stop eta (default 1e-4; the inner solve
- * also stops once its residual is below tol * ||b||). */
+/* Refinement controls for RORBK_REFINE (not in the paper: FP32/BF16 inner
+ * passes of Algorithm 1 corrected by an FP64 outer residual): inner iterations
+ * per FP64 correction (default 50) and the inner relative stop eta (default
+ * 1e-4; the inner solve also stops once its residual is below tol * ||b||).
+ * RORBK_ERR_INVALID_ARG if inner_iters < 1 or eta is negative or not finite. */
 int ror_bk_set_refine(rorbk_handle h, int64_t inner_iters, double eta);
 
-/* Residual-pass timings of the last RORBK_PROFILE solve: out[0] = mean
- * duration (ms) of the sampled inner (working-precision) residual launches,
- * out[1] = their count, out[2] = mean duration (ms) of the FP64 outer residual
- * launches of a REFINE solve, out[3] = their count. */
+/* Timings of the full residual pass (Algorithm 1's r = b - A x, the O(mn)
+ * part of every iteration, Section 3.1) in the last RORBK_PROFILE solve, into
+ * out4_host (host, 4 doubles): out[0] = mean duration (ms) of the sampled
+ * inner (working-precision) residual launches, out[1] = their count, out[2] =
+ * mean duration (ms) of the FP64 outer residual launches of a REFINE solve,
+ * out[3] = their count. */
 int ror_bk_get_profile(rorbk_handle h, double *out4_host);
 
-/* Static description of a status code. */
+/* Static description of a status code (the RORBK_ERR_* list above; the
+ * paper defines no error handling). */
 const char *ror_bk_error_string(int code);
 
-/* Details of the calling thread's last failure ("" if none). */
+/* Details of the calling thread's last failure ("" if none); library
+ * diagnostics, not a step of the method. */
 const char *ror_bk_last_error_message(void);
 
 #ifdef __cplusplus

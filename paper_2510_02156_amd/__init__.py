@@ -14,7 +14,7 @@ from .binding import (RORBK_CHECKPOINT, RORBK_PROFILE, RORBK_RECORD, RORBK_REFIN
                       RorBkError, lib, ror_bk_backward, ror_bk_destroy,
                       ror_bk_get_block_inverse, ror_bk_get_form, ror_bk_get_profile,
                       ror_bk_get_record,
-                      ror_bk_get_setup,
+                      ror_bk_get_setup, ror_bk_partition,
                       ror_bk_fabgmres, ror_bk_get_sizes, ror_bk_initial_solution,
                       ror_bk_residual, ror_bk_sample, ror_bk_set_proposal,
                       ror_bk_set_refine, ror_bk_set_replay, ror_bk_setup, ror_bk_solve,
@@ -39,6 +39,9 @@ class Solver:
         self.m, self.n = self.desc.m, self.desc.n
         self.dtype = self.desc.dtype
         self._b_keep = None
+        # every solve on the handle replaces its record; backward checks that
+        # the record it differentiates is still the one its forward made
+        self.generation = 0
 
     # vector dtype of plain solves on this storage
     def vec_dtype(self, refine: bool = False):
@@ -57,6 +60,7 @@ class Solver:
                 (RORBK_REPLAY if replay else 0) | (RORBK_CHECKPOINT if checkpoint_every else 0) | \
                 (RORBK_PROFILE if profile else 0)
         self._b_keep = b
+        self.generation += 1
         info = ror_bk_solve(self.h, b, x, seed, tol, max_iters, start_iter, flags,
                             checkpoint_every)
         return x, info
@@ -109,6 +113,7 @@ class Solver:
             x = torch.zeros(self.n, dtype=torch.float64, device=b.device)
         if b.dtype != torch.float64 or x.dtype != torch.float64:
             raise TypeError("flexible AB-GMRES works on double vectors")
+        self.generation += 1
         info = ror_bk_fabgmres(self.h, b, x, seed, tol, max_outer, inner_iters, eta)
         return x, info
 
@@ -157,9 +162,15 @@ class RorBkFunction(torch.autograd.Function):
                      record=not checkpoint_every, checkpoint_every=checkpoint_every)
         ctx.solver = solver
         ctx.b = bb
+        ctx.generation = solver.generation
         return x
 
     @staticmethod
     def backward(ctx, gx):
+        if ctx.solver.generation != ctx.generation:
+            raise RuntimeError(
+                "RorBkFunction.backward: the solver ran another solve after this forward, "
+                "so its record belongs to a different run; give each differentiated "
+                "forward its own Solver, or run its backward before the next solve")
         gb, gx0 = ctx.solver.backward(gx.contiguous())
         return gb, gx0, None, None, None, None

@@ -32,7 +32,7 @@ RORBK_REFINE, RORBK_RECORD, RORBK_REPLAY, RORBK_CHECKPOINT = 1, 2, 4, 8
 RORBK_PROFILE = 16
 
 EXPORTS = [
-    "ror_bk_setup", "ror_bk_solve", "ror_bk_backward", "ror_bk_destroy",
+    "ror_bk_partition", "ror_bk_setup", "ror_bk_solve", "ror_bk_backward", "ror_bk_destroy",
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
     "ror_bk_get_block_inverse", "ror_bk_get_form", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
     "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
@@ -64,7 +64,8 @@ class rorbk_matrix(C.Structure):
 
 class rorbk_info(C.Structure):
     _fields_ = [("iters", C.c_int64), ("rrn", C.c_double), ("converged", C.c_int32),
-                ("n_refine", C.c_int32), ("t_solve_s", C.c_double)]
+                ("n_refine", C.c_int32), ("t_solve_s", C.c_double), ("t_setup_s", C.c_double),
+                ("rrn_test", C.c_double)]
 
 
 _lib = None
@@ -81,6 +82,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
         sig = {
+            "ror_bk_partition": (C.c_int, [I64, I64, P, P]),
             "ror_bk_setup": (C.c_int, [C.POINTER(rorbk_matrix), I64, D, P, C.POINTER(P)]),
             "ror_bk_solve": (C.c_int, [P, P, P, C.c_uint64, D, I64, I64, C.c_uint32, I64,
                                        C.POINTER(rorbk_info)]),
@@ -149,6 +151,17 @@ def _dtype_code(t) -> int:
 
 # ------------------------------------------------------------ raw entry points
 
+def ror_bk_partition(m: int, block_rows: int) -> np.ndarray:
+    """The k+1 block offsets (host computation in the library, no device)."""
+    k = C.c_int64()
+    _check(lib().ror_bk_partition(int(m), int(block_rows), None, C.byref(k)),
+           "ror_bk_partition")
+    off = np.zeros(k.value + 1, dtype=np.int64)
+    _check(lib().ror_bk_partition(int(m), int(block_rows), _np_ptr(off), C.byref(k)),
+           "ror_bk_partition")
+    return off
+
+
 def ror_bk_setup(A=None, block_rows: int = 1, lam: float = 0.0, stream=None, *,
                  rowptr=None, colidx=None, values=None, shape=None, A64=None):
     """Set up a handle.  Dense: ``A`` a 2-D CUDA tensor with unit column stride
@@ -188,7 +201,8 @@ def ror_bk_solve(h, b, x, seed: int, tol: float, max_iters: int, start_iter: int
                               int(max_iters), int(start_iter), int(flags),
                               int(checkpoint_every), C.byref(info)), "ror_bk_solve")
     return {"iters": info.iters, "rrn": info.rrn, "converged": bool(info.converged),
-            "n_refine": info.n_refine, "t_solve_s": info.t_solve_s}
+            "n_refine": info.n_refine, "t_solve_s": info.t_solve_s,
+            "t_setup_s": info.t_setup_s, "rrn_test": info.rrn_test}
 
 
 def ror_bk_backward(h, grad_x, grad_b, grad_x0):
@@ -284,7 +298,7 @@ def ror_bk_fabgmres(h, b, x, seed: int, tol: float, max_outer: int, inner_iters:
                                  int(max_outer), int(inner_iters), float(eta), C.byref(info)),
            "ror_bk_fabgmres")
     return {"inner_iters": info.iters, "outer": info.n_refine, "converged": bool(info.converged),
-            "rrn": info.rrn}
+            "rrn": info.rrn, "t_setup_s": info.t_setup_s}
 
 
 def ror_bk_set_replay(h, tau, I, iters: int):

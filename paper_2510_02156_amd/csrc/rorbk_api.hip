@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -485,9 +486,24 @@ int ror_bk_destroy(rorbk_handle h) {
     return RORBK_OK;
 }
 
+int ror_bk_partition(int64_t m, int64_t block_rows, int64_t *offsets_host, int64_t *k) {
+    g_msg[0] = 0;
+    if (!k) return fail(RORBK_ERR_INVALID_ARG, "k pointer is NULL");
+    if (m < 1) return fail(RORBK_ERR_INVALID_ARG, "m = %lld < 1", (long long)m);
+    if (block_rows < 1 || block_rows > m)
+        return fail(RORBK_ERR_INVALID_ARG, "block_rows %lld outside [1, m=%lld]",
+                    (long long)block_rows, (long long)m);
+    const int64_t nb = m / block_rows, q = m / nb, rem = m - nb * q;
+    *k = nb;
+    if (offsets_host)
+        for (int64_t t = 0; t <= nb; ++t) offsets_host[t] = t * q + std::min(t, rem);
+    return RORBK_OK;
+}
+
 int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void *stream,
                  rorbk_handle *out) {
     g_msg[0] = 0;
+    const auto t_entry = std::chrono::steady_clock::now();
     if (!out) return fail(RORBK_ERR_INVALID_ARG, "out handle pointer is NULL");
     *out = nullptr;
     if (!A) return fail(RORBK_ERR_INVALID_ARG, "matrix descriptor is NULL");
@@ -717,6 +733,8 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
                              ? "a block Gram A_t^T A_t + lambda I is not positive definite"
                              : "a block Gram A_t A_t^T + lambda I is not positive definite"));
     }
+    h->t_setup_s =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_entry).count();
     *out = h;
     return RORBK_OK;
 }
@@ -863,6 +881,8 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
     hipStream_t s = h->stream;
     const int64_t m = L.m, n = L.n, M1 = max_outer + 1;
     h->rec_valid = 0;
+    h->rec_I_valid = 0;
+    h->rec_iters = 0;
     h->profile = 0;
     // workspaces of this call
     double *V = nullptr, *Z = nullptr, *small = nullptr;
@@ -969,6 +989,8 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
         info->converged = conv ? 1 : 0;
         const Ctrl &c = *h->h_ctrl;
         info->rrn = c.bnorm2 > 0 ? std::sqrt(c.rnorm2 / c.bnorm2) : 0.0;
+        info->rrn_test = info->rrn;
+        info->t_setup_s = h->t_setup_s;
     }
     return RORBK_OK;
 }
@@ -1059,7 +1081,8 @@ int ror_bk_get_record(rorbk_handle h, int32_t *tau_host, int32_t *I_host, double
     if (it == 0) return RORBK_OK;
     if (tau_host) HIPCHK(hipMemcpyAsync(tau_host, h->d_tau, 4 * 3 * it, hipMemcpyDeviceToHost, h->stream));
     if (I_host) {
-        if (!h->d_recI) return fail(RORBK_ERR_NOT_RECORDED, "greedy sets were not recorded");
+        if (!h->d_recI || !h->rec_I_valid)
+            return fail(RORBK_ERR_NOT_RECORDED, "the last solve did not record its greedy sets");
         HIPCHK(hipMemcpyAsync(I_host, h->d_recI, 4 * it * h->L.K, hipMemcpyDeviceToHost, h->stream));
     }
     if (rrn_host) HIPCHK(hipMemcpyAsync(rrn_host, h->d_recR, 8 * it, hipMemcpyDeviceToHost, h->stream));
@@ -1093,7 +1116,10 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
     rorbk_info inf;
     memset(&inf, 0, sizeof(inf));
     inf.rrn = NAN;
+    inf.rrn_test = NAN;
+    inf.t_setup_s = h->t_setup_s;
     h->rec_valid = 0;
+    h->rec_I_valid = 0;
     h->rec_iters = 0;
     h->profile = (flags & RORBK_PROFILE) ? 1 : 0;
     h->prof_in_ms = h->prof_out_ms = 0.0;
@@ -1134,17 +1160,38 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
         if (rc == RORBK_OK) {
             inf.iters = ran;
             inf.converged = stopped ? 1 : 0;
-            const Ctrl &c = *h->h_ctrl;
-            inf.rrn = c.bnorm2 > 0 ? std::sqrt(c.rnorm2 / c.bnorm2) : 0.0;
+            const Ctrl c = *h->h_ctrl;
+            inf.rrn_test = c.bnorm2 > 0 ? std::sqrt(c.rnorm2 / c.bnorm2) : 0.0;
+            inf.rrn = inf.rrn_test;
             h->rec_iters = ran;
             if (record || ckpt) {
                 h->rec_valid = ckpt ? 2 : 1;
+                h->rec_I_valid = 1;
                 h->rec_converged = inf.converged;
                 h->ckpt_every = ckpt ? checkpoint_every : 0;
                 h->rec_b = b;
                 h->rec_seed = seed;
                 h->rec_vec = vec;
                 h->rec_thr = c.thr;
+            }
+            if (!stopped) {
+                // the greedy update after the last stop test changed x: one
+                // more residual pass measures the iterate returned
+                HIPCHK(residual(h, h->A, L.dtype, h->aligned, vec, x, h->d_axp));
+                SelectArgs sa;
+                memset(&sa, 0, sizeof(sa));
+                sa.vec = vec;
+                sa.b = b;
+                sa.axp = h->d_axp;
+                sa.nseg = L.nseg;
+                sa.r = h->d_r;
+                sa.skip_topk = 1;
+                HIPCHK(launch_select(h, sa, s));
+                HIPCHK(hipMemcpyAsync(h->h_ctrl, h->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                const Ctrl &cf = *h->h_ctrl;
+                if (cf.status) return fail(cf.status, "non-finite residual of the returned x");
+                inf.rrn = cf.bnorm2 > 0 ? std::sqrt(cf.rnorm2 / cf.bnorm2) : 0.0;
             }
         }
     } else {
@@ -1233,6 +1280,7 @@ int ror_bk_solve(rorbk_handle h, const void *b, void *x, uint64_t seed, double t
         inf.iters = total;
         inf.converged = conv ? 1 : 0;
         inf.rrn = rrn;
+        inf.rrn_test = rrn;
         inf.n_refine = nref;
         h->rec_iters = total;
     }

@@ -69,6 +69,7 @@ struct rorbk_handle_s {
     hipStream_t stream;
     int32_t ncu;              // compute units of the device
     double lambda;
+    double t_setup_s;         // wall time of ror_bk_setup
     int32_t aligned;          // 16-byte vector loads allowed on the matrix
     int32_t aligned64;        // same for the FP64 master copy
     const void *A;            // working matrix values (non-owning)
@@ -127,6 +128,7 @@ struct rorbk_handle_s {
     int64_t rec_cap;
     int64_t rec_iters;        // iterations recorded by the last solve
     int32_t rec_valid;        // 1 after a RECORD solve, 2 after CHECKPOINT
+    int32_t rec_I_valid;      // 1 while d_recI holds the greedy sets of the last solve
     int32_t rec_converged;
     int64_t ckpt_every;
     void *d_ckpt;             // x checkpoints (vector type) [(cap/c)+1][n]

@@ -77,9 +77,55 @@ def test_struct_layouts_match_header():
     assert C.sizeof(binding.rorbk_matrix) == 8 + 3 * 8 + 3 * 8 + 8 + 8
     assert binding.rorbk_matrix.values.offset == 32
     assert binding.rorbk_matrix.values_f64.offset == 64
-    # rorbk_info: int64, double, 2 int32, double
-    assert C.sizeof(binding.rorbk_info) == 32
+    # rorbk_info: int64, double, 2 int32, 3 doubles
+    assert C.sizeof(binding.rorbk_info) == 48
     assert binding.rorbk_info.t_solve_s.offset == 24
+    assert binding.rorbk_info.t_setup_s.offset == 32
+    assert binding.rorbk_info.rrn_test.offset == 40
+    # and the header lists the same fields in the same order
+    body = re.search(r"typedef struct rorbk_info \{(.*?)\} rorbk_info;", _header(), re.S).group(1)
+    names = re.findall(r"^\s*\w+\s+(\w+);", re.sub(r"/\*.*?\*/", "", body, flags=re.S), re.M)
+    assert names == [f[0] for f in binding.rorbk_info._fields_]
+
+
+def test_partition_entry_point_matches_oracle():
+    """ror_bk_partition (host, no handle, no device) against the oracle's
+    partition for every block size 1..m on several m, bit for bit; the
+    argument checks refuse the degenerate requests."""
+    from paper_2510_02156_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("librorbk.so not built")
+    import numpy as np
+
+    import oracle as O
+    for m in (1, 2, 3, 7, 64, 100, 257, 1000, 2001):
+        for br in range(1, m + 1):
+            got = binding.ror_bk_partition(m, br)
+            ref = O.partition(m, br)
+            assert got.dtype == np.int64 and np.array_equal(got, ref), (m, br)
+    # the full sizes of the dense, tall, sparse, wide and differentiation workloads
+    for m, br in ((2000, 20), (100000, 64), (200000, 128), (2000, 32), (20000, 50)):
+        assert np.array_equal(binding.ror_bk_partition(m, br), O.partition(m, br))
+    L = binding.lib()
+    k = C.c_int64(-1)
+    for m, br in ((0, 1), (5, 0), (5, 6), (-3, 1)):
+        assert L.ror_bk_partition(m, br, None, C.byref(k)) == binding.RORBK_ERR_INVALID_ARG
+    assert L.ror_bk_partition(10, 3, None, None) == binding.RORBK_ERR_INVALID_ARG
+    assert L.ror_bk_partition(10, 3, None, C.byref(k)) == binding.RORBK_OK and k.value == 3
+
+
+def test_every_declaration_cites_the_paper_or_says_why_not():
+    """Each entry point's comment names the passage of the paper it implements
+    (an algorithm, section or lemma), or states that it is not a step of the
+    method."""
+    text = _header()
+    for name in _declared_functions():
+        m = re.search(r"/\*((?:(?!\*/).)*?)\*/\s*(?:int|const char \*)\s*" + name + r"\s*\(",
+                      text, re.S)
+        assert m, f"{name} has no comment right above it"
+        doc = m.group(1)
+        assert re.search(r"Algorithm \d|Section \d|Sec\. \d|Lemma \d|not in the paper|"
+                         r"paper defines no|not a step of the method|callers that cannot", doc), name
 
 
 def test_block_size_limits_refused_before_any_device_call():

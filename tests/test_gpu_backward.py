@@ -179,3 +179,35 @@ def test_differentiation_workload_full_size():
         e = np.zeros(len(b)); e[i] = h
         fd = (loss(b + e) - loss(b - e)) / (2 * h)
         assert fd == pytest.approx(float(host(gb64)[i]), rel=1e-5, abs=1e-8)
+
+
+def test_autograd_interleaved_forwards_are_refused():
+    """Two differentiated forwards on one Solver before their backwards: the
+    second replaced the handle's record, so the first graph's backward raises
+    instead of returning the second run's gradients; with one Solver per
+    forward both backwards match the oracle's adjoint of their own run."""
+    s, br, lam = setup_case()
+    iters = 12
+    sol = P.Solver(dev(s["A"]), br, lam)
+    b1 = dev(s["b"]).requires_grad_(True)
+    b2 = dev(2.0 * s["b"]).requires_grad_(True)
+    x0 = dev(s["x0"])
+    xa = P.RorBkFunction.apply(b1, x0, sol, 3, iters, 0)
+    xb = P.RorBkFunction.apply(b2, x0, sol, 4, iters, 0)
+    xt = dev(s["xt"])
+    with pytest.raises(RuntimeError, match="another solve"):
+        ((xa - xt) ** 2).sum().backward()
+    ((xb - xt) ** 2).sum().backward()        # the latest forward still differentiates
+    assert b2.grad is not None
+    # separate solvers: each graph keeps its own record
+    s1, s2 = P.Solver(dev(s["A"]), br, lam), P.Solver(dev(s["A"]), br, lam)
+    c1 = dev(s["b"]).requires_grad_(True)
+    c2 = dev(2.0 * s["b"]).requires_grad_(True)
+    ya = P.RorBkFunction.apply(c1, x0, s1, 3, iters, 0)
+    yb = P.RorBkFunction.apply(c2, x0, s2, 4, iters, 0)
+    for y, c, so in ((ya, c1, s1), (yb, c2, s2)):
+        ((y - xt) ** 2).sum().backward()
+        rec = so.record()
+        g = 2 * (host(y.detach()) - s["xt"])
+        rb, _ = O.backward(s["A"], br, lam, rec["tau"], rec["I"], iters, False, g)
+        assert rel(host(c.grad), rb) < 1e-10

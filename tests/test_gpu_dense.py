@@ -18,7 +18,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 import paper_2510_02156_amd as P  # noqa: E402
-from tests.gpu_util import dev, host, rel  # noqa: E402
+from tests.gpu_util import bf16_tensor, bf16_values, dev, host, rel  # noqa: E402
 
 SHAPES = [
     # m, n, block_rows, lam, cond   (ragged partitions / column tails)
@@ -151,14 +151,23 @@ def test_free_running_matches_oracle(m, n, br, lam, cond):
     assert rel(host(x), ref["x"]) < 1e-10
 
 
-@pytest.mark.parametrize("m,n,br", [(400, 9001, 16), (420, 8960, 20)])
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+MULTI_SLAB = [
+    (400, 9001, 16),    # FP64 3 rows per thread (prefetch), odd n misaligns FP64 rows
+    (420, 8960, 20),
+    (1000, 8704, 50),   # FP64 9 rows per thread with the prefetch
+    (1100, 8400, 100),  # FP64 21 rows per thread, no prefetch; greedy set of 100 rows
+]
+
+
+@pytest.mark.parametrize("m,n,br", MULTI_SLAB)
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
 def test_multi_slab_update_workgroups(m, n, br, storage):
     """More than 64 slabs of 128 columns: each update workgroup takes two and
     loads the second while the first is reduced (ragged last slab; odd n also
-    misaligns the FP64 rows).  FP64 storage against the oracle; FP32 storage
-    replayed on the oracle's draws and greedy sets against the oracle run on
-    the FP32-rounded matrix."""
+    misaligns the FP64 rows).  The block sizes cover each rows-per-thread
+    instantiation of the step kernel.  FP64 storage against the oracle;
+    FP32 and BF16 storage replayed on the oracle's draws and greedy sets
+    against the oracle run on the rounded matrix."""
     s = make(m, n, 1e3)
     lam = 1e-4
     iters = 20
@@ -176,15 +185,21 @@ def test_multi_slab_update_workgroups(m, n, br, storage):
         print(f"multi-slab f64 m={m} n={n}: rel err {e:.2e}", flush=True)
         assert e < 1e-10
     else:
-        Av = s["A"].astype(np.float32).astype(np.float64)
+        if storage == "f32":
+            Av = s["A"].astype(np.float32).astype(np.float64)
+            At = dev(s["A"], torch.float32)
+        else:
+            Av = bf16_values(s["A"])
+            At = bf16_tensor(s["A"])
         b = Av @ s["xstar"]
         ref = O.solve(Av, br, lam, b, seed=31, max_iters=iters)
-        sol = P.Solver(dev(s["A"], torch.float32), br, lam)
+        sol = P.Solver(At, br, lam)
         sol.set_replay(ref["tau"], ref["I"], iters)
         x, _ = sol.solve(dev(b, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
         assert x.dtype == torch.float32
         e = rel(host(x), ref["x"])
-        print(f"multi-slab f32 m={m} n={n}: rel err vs FP64 oracle {e:.2e}", flush=True)
+        print(f"multi-slab {storage} m={m} n={n} br={br}: rel err vs FP64 oracle {e:.2e}",
+              flush=True)
         assert e < 1e-4
 
 
@@ -234,4 +249,43 @@ def test_errors():
     assert e.value.code == P.RORBK_ERR_INVALID_ARG
     with pytest.raises(P.RorBkError) as e:
         sol.backward(dev(np.zeros(30)))
+    assert e.value.code == P.RORBK_ERR_NOT_RECORDED
+
+
+def test_info_rrn_is_that_of_the_returned_iterate():
+    """rorbk_info.rrn is ||b - A x|| / ||b|| of the x returned: after a solve
+    that ends at its cap (one greedy update after the last stop test) it is
+    measured again; rrn_test keeps the last stop test, which the RRN history
+    ends with; t_setup_s reports the setup's wall time."""
+    s = make(1000, 300, 1e4)
+    sol = P.Solver(dev(s["A"]), 20, 1e-3)
+    b = dev(s["b"])
+    x, info = sol.solve(b, seed=9, tol=0.0, max_iters=25, record=True)
+    rr = np.linalg.norm(s["b"] - s["A"] @ host(x)) / np.linalg.norm(s["b"])
+    assert not info["converged"]
+    assert info["rrn"] == pytest.approx(rr, rel=1e-10)
+    hist = sol.record()["rrn"]
+    assert info["rrn_test"] == pytest.approx(hist[-1], rel=1e-14)
+    assert 0.0 < info["t_setup_s"] < 60.0
+    # a converged solve returns the tested iterate: both fields agree
+    x2, i2 = sol.solve(b, seed=9, tol=0.2, max_iters=500)
+    assert i2["converged"] and i2["rrn"] == i2["rrn_test"] < 0.2
+    rr2 = np.linalg.norm(s["b"] - s["A"] @ host(x2)) / np.linalg.norm(s["b"])
+    assert i2["rrn"] == pytest.approx(rr2, rel=1e-10)
+
+
+def test_record_of_a_later_solve_without_greedy_sets_is_refused():
+    """A solve that does not record its greedy sets replaces the record: the
+    sets of an older recorded solve are not returned any more."""
+    s = make(600, 120, 1e3)
+    sol = P.Solver(dev(s["A"]), 20, 1e-3)
+    b = dev(s["b"])
+    sol.solve(b, seed=3, tol=0.0, max_iters=30, record=True)
+    rec = sol.record()
+    assert rec["iters"] == 30 and rec["I"] is not None
+    sol.solve(b, seed=4, tol=0.0, max_iters=20)          # not recorded
+    rec2 = sol.record()
+    assert rec2["iters"] == 20 and rec2["I"] is None
+    with pytest.raises(P.RorBkError) as e:
+        sol.backward(torch.ones(120, dtype=torch.float64, device="cuda:0"))
     assert e.value.code == P.RORBK_ERR_NOT_RECORDED
