@@ -207,3 +207,45 @@ def test_table5_full_size():
     e = rel(host(x), replayed_iteration(A, w["b"], lam, off, tau, I))
     print(f"table 5 full size: replayed iteration rel err {e:.2e}", flush=True)
     assert e < 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_tall_cond10_reaches_1e8_like_the_oracle(golden_dir):
+    """The supplementary system of the tall workload's shape, blocks and
+    generator at cond 10: the FP64 GPU solve passes the stop test RRN < 1e-8
+    at the oracle's iteration (tests/golden/tall_cond10_100000x2000.txt,
+    written by the oracle) with x equal at the 64 sampled indices; the FP32-
+    and BF16-storage solves with FP64 refinement also reach 1e-8, measured in
+    FP64 on the returned x."""
+    from tests.conftest import read_golden
+    g = read_golden(f"{golden_dir}/tall_cond10_100000x2000.txt")
+    w = make("tall_cond10_100000x2000")
+    A, br, lam, seed, tol, cap = (w["A"], w["block_rows"], w["lam"], w["seed"], w["tol"],
+                                  w["max_iters"])
+    A64 = dev(A)
+    b = dev(w["b"])
+    sol = P.Solver(A64, br, lam)
+    x, info = sol.solve(b, seed=seed, tol=tol, max_iters=cap)
+    idx = np.array([int(v) for v in g["x_idx"]])
+    val = np.array([float(v) for v in g["x_val"]])
+    e = rel(host(x)[idx], val)
+    print(f"cond-10 tall FP64: GPU {info['iters']} iterations (oracle {g['iters'][0]}), rrn "
+          f"{info['rrn']:.3e} (oracle {float(g['rrn'][0]):.3e}), sampled x rel err {e:.2e}",
+          flush=True)
+    assert info["converged"] and info["iters"] == int(g["iters"][0])
+    assert info["rrn"] == pytest.approx(float(g["rrn"][0]), rel=1e-6)
+    assert e < 1e-9
+    for name, At in (("f32", A64.float()), ("bf16", None)):
+        if At is None:
+            from tests.gpu_util import bf16_tensor
+            At = bf16_tensor(A)
+        sm = P.Solver(At, br, lam, A64=A64)
+        xm, im = sm.solve(b, seed=seed, tol=tol, max_iters=cap, refine=True)
+        rr = sol.residual(b, xm)[2]
+        em = rel(host(xm)[idx], val)
+        print(f"cond-10 tall {name}+FP64 refinement: {im['iters']} iterations, "
+              f"{im['n_refine']} corrections, FP64 rrn {rr:.3e}, sampled x vs oracle {em:.2e}",
+              flush=True)
+        assert im["converged"] and rr < tol and im["rrn"] == pytest.approx(rr, rel=1e-6)
+        assert em < 1e-6
+        sm.close()

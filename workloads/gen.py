@@ -164,6 +164,12 @@ WORKLOADS = {
                               block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
     "unif_100000x20000": dict(cfg=9, kind="unif1", m=100000, n=20000,
                               block_rows=1000, lam=None, tol=1e-6, max_iters=2000),
+    # supplementary system for time to 1e-8: the tall workload's shape, blocks,
+    # regularisation and generator at a low condition number, where plain
+    # ROR-BK reaches a relative residual of 1e-8 within the 5000-iteration
+    # cap (at cond 1e8 it levels off near 5e-3)
+    "tall_cond10_100000x2000": dict(cfg=11, kind="dense", m=100000, n=2000, cond=10.0,
+                                    block_rows=64, lam=1e-4, tol=1e-8, max_iters=5000),
     # tall and narrow with the paper's 100 blocks: blocks of 2000 rows against
     # 500 columns, the case for the column form of the block solve (Sec. 3.1)
     "colform_200000x500": dict(cfg=8, kind="dense", m=200000, n=500, cond=1e6,
