@@ -18,10 +18,29 @@ the column form).
 
 Timed: the mixed-precision solve (FP32 storage for the inner passes, FP64
 outer residual and refinement; `value`) and the all-FP64 solve on the same
-matrix, inputs resident in HBM.  The residual-pass kernel is timed with HIP
-events inside the solve (RORBK_PROFILE).  The FP64 CPU oracle is timed on a
-bounded sample of the same workload on the host cores (cpu_baseline), and the
-GPU solves are compared with it over that sample.
+matrix for --steps outer iterations, inputs resident in HBM.  The
+residual-pass kernel is timed with HIP events inside the solve
+(RORBK_PROFILE).
+
+`time_to_tol`: the same solves (and the BF16 one) under the workload's own
+stop rule, relative residual below its tolerance or its iteration cap (5000
+for the tall workload), with the iterations, whether the tolerance was reached
+and the residual of the returned x.  On the tall workload the cond-1e8 matrix
+levels off near 5e-3, so the same solves also run on a labelled supplementary
+system of the same shape, blocks and generator at cond 10
+(``tall_cond10_100000x2000``), where both reach 1e-8; the FP64 oracle's
+iteration count on it (tests/golden/tall_cond10_100000x2000.txt) is reported
+beside the GPU's.
+
+``--workload diff_20000x1000``: the differentiation workload instead, a
+300-iteration FP32 forward with x checkpointed every 20 iterations and the
+backward to dL/db and dL/dx0 (recomputation of the greedy sets against the
+adjoint steps), errors against the FP64 oracle's adjoint.
+
+The FP64 CPU oracle is timed on a bounded sample of the same workload on the
+host cores (cpu_baseline: median of three runs on all threads, one run on one
+thread, the host CPU model), and the GPU solves are compared with it over that
+sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -67,6 +86,38 @@ def measured_traffic(workload: str, mixed: str):
         with open(os.path.join(ROOT, "paper_2510_02156_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return int(tb.group(1)) if h.hexdigest() == hs.group(1) else None
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and topology (lscpu), and the CPUs this process
+    may run on."""
+    import subprocess
+    out = {"nproc_affinity": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+    try:
+        text = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in text.splitlines():
+            if ":" not in line:
+                continue
+            key, val = (t.strip() for t in line.split(":", 1))
+            if key in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                       "CPU(s)", "NUMA node(s)"):
+                out[key] = val
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return out
+
+
+def read_golden(path: str) -> dict:
+    out = {}
+    if not os.path.exists(path):
+        return out
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                key, *vals = line.split()
+                out[key] = vals
+    return out
 
 
 def copy_calibration(mib: int):
@@ -118,11 +169,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "diff_20000x1000":
+        bench_diff(args, dev)
+        return
     t0 = time.time()
     w = make(args.workload)
     log(f"generated {args.workload} in {time.time() - t0:.1f}s")
     bh = w["b"]
     br, lam, tol, seed = w["block_rows"], w["lam"], w["tol"], w["seed"]
+    cap = w["max_iters"]
     b = torch.from_numpy(bh).to(dev)
     csr = w["format"] == "csr"
     if csr:
@@ -135,16 +190,12 @@ def main():
         V64 = torch.from_numpy(w["val"]).to(dev)
         V32 = V64.float()
         torch.cuda.synchronize()
-        t0 = time.time()
         s64 = P.Solver(None, br, lam, rowptr=rowptr, colidx=colidx, values=V64, shape=(m, n))
-        torch.cuda.synchronize()
-        t_setup64 = time.time() - t0
-        t0 = time.time()
         smix = P.Solver(None, br, lam, rowptr=rowptr, colidx=colidx, values=V32, shape=(m, n),
                         A64=V64)
         torch.cuda.synchronize()
-        t_setupmix = time.time() - t0
         oracle_A = w
+        Abf = A32 = A64 = None
     else:
         A64h = w["A"]
         m, n = A64h.shape
@@ -153,17 +204,15 @@ def main():
         A32 = A64.float()
         Abf = torch.from_numpy(to_bf16_bits(A64h).view(np.int16)).view(torch.bfloat16).to(dev)
         torch.cuda.synchronize()
-        t0 = time.time()
         s64 = P.Solver(A64, br, lam)
-        torch.cuda.synchronize()
-        t_setup64 = time.time() - t0
         Amix = A32 if args.mixed == "f32" else Abf
-        t0 = time.time()
         smix = P.Solver(Amix, br, lam, A64=A64)
         torch.cuda.synchronize()
-        t_setupmix = time.time() - t0
         oracle_A = A64h
     smix.set_refine(args.inner, 1e-4)
+    # setup wall times as the library measured them (rorbk_info.t_setup_s)
+    t_setup64 = s64.solve(b, seed=seed, tol=0.0, max_iters=1)[1]["t_setup_s"]
+    t_setupmix = smix.solve(b, seed=seed, tol=0.0, max_iters=1, refine=True)[1]["t_setup_s"]
     log(f"setup: fp64 {t_setup64:.3f}s, mixed-{args.mixed} {t_setupmix:.3f}s "
         f"(k={s64.k}, K={s64.K})")
 
@@ -176,11 +225,12 @@ def main():
             return nnz * (es + 4) + (m + 1) * 8 + n * xs + m * 8
         return m * n * es + n * xs + m * 8
 
-    def run(sol, refine, iters, profile=False):
+    def run(sol, refine, iters, profile=False, rhs=None, stop=None):
         x = torch.zeros(n, dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, info = sol.solve(b, x, seed=seed, tol=tol, max_iters=iters, refine=refine,
+        x, info = sol.solve(b if rhs is None else rhs, x, seed=seed,
+                            tol=tol if stop is None else stop, max_iters=iters, refine=refine,
                             profile=profile)
         torch.cuda.synchronize()
         return x, info, time.perf_counter() - t
@@ -189,26 +239,27 @@ def main():
     run(smix, True, args.warmup)
     if not args.skip_extra:
         run(s64, False, args.warmup)
-    # timed: mixed (value), then FP64
+    # timed: mixed (value), then FP64, each for --steps outer iterations
     xm, im, tm = run(smix, True, K, profile=True)
     prof_m = smix.profile()
     marks = [i for i in (1, 10, 100, 500, 1000, 2000, 3000, 4000, 5000, K) if i <= K]
 
-    def curve(sol):
+    def curve(sol, pts=None):
         h = sol.record()["rrn"]
-        return {str(i): float(h[i - 1]) for i in sorted(set(marks)) if i <= len(h)}
+        return {str(i): float(h[i - 1]) for i in sorted(set(pts or marks)) if i <= len(h)}
 
     curve_m = curve(smix)
     log(f"mixed-{args.mixed}: {tm:.3f}s for {im['iters']} iters, rrn {im['rrn']:.3e}, "
         f"converged {im['converged']}, refine steps {im['n_refine']}")
     res = {}
+    i64 = None
     if not args.skip_extra:
         x64, i64, t64 = run(s64, False, K, profile=True)
         prof_64 = s64.profile()
         res["rrn_curve"] = {"mixed": curve_m, "fp64": curve(s64)}
         log(f"fp64: {t64:.3f}s for {i64['iters']} iters, rrn {i64['rrn']:.3e}")
         res["fp64"] = {"time_s": t64, "iters": i64["iters"], "rrn": i64["rrn"],
-                       "converged": i64["converged"],
+                       "rrn_test": i64["rrn_test"], "converged": i64["converged"],
                        "resid_kernel_ms": prof_64["inner_ms"],
                        "resid_GBs": resid_bytes(8, 8) / (prof_64["inner_ms"] * 1e-3) / 1e9
                        if prof_64["inner_ms"] > 0 else None}
@@ -219,6 +270,47 @@ def main():
                                     "fp64": float(s64.residual(b, x64)[2])}
         res["rel_err_to_xstar"] = {"mixed": float(np.linalg.norm(xm.cpu().numpy() - xs) / np.linalg.norm(xs)),
                                    "fp64": float(np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs))}
+
+        # ---- time to tolerance under the workload's own stop rule
+        def to_tol(sol, refine, rhs=None, stop=None, cap_=None):
+            x, info, t = run(sol, refine, cap_ or cap, rhs=rhs, stop=stop)
+            return x, {"reached": bool(info["converged"]), "iters": info["iters"], "time_s": t,
+                       "rrn": info["rrn"], "rrn_test": info["rrn_test"],
+                       "n_refine": info["n_refine"]}
+
+        ttt = {"workload": args.workload, "tol": tol, "cap_iters": cap,
+               "rrn_of_returned_x": "FP64 for fp64 and the refined mixed solves"}
+        _, ttt["fp64"] = to_tol(s64, False)
+        _, ttt[f"mixed_{args.mixed}"] = to_tol(smix, True)
+        soth = None
+        if not csr:
+            other = "bf16" if args.mixed == "f32" else "f32"
+            soth = P.Solver(Abf if other == "bf16" else A32, br, lam, A64=A64)
+            soth.set_refine(args.inner, 1e-4)
+            run(soth, True, args.warmup)
+            _, ttt[f"mixed_{other}"] = to_tol(soth, True)
+        f64t = ttt["fp64"]["time_s"]
+        for key in [k for k in ttt if k.startswith("mixed_")]:
+            ttt[key]["speedup_vs_fp64"] = f64t / ttt[key]["time_s"]
+        if not (ttt["fp64"]["reached"] and ttt[f"mixed_{args.mixed}"]["reached"]):
+            # neither (or not both) reach the tolerance within the cap: compare
+            # at a tolerance both reach, 1e-2 (the plateau of the cond-1e8
+            # matrices is near 5e-3), as well as at the cap
+            common = 1e-2
+            tc = {"tol": common}
+            _, tc["fp64"] = to_tol(s64, False, stop=common)
+            _, tc[f"mixed_{args.mixed}"] = to_tol(smix, True, stop=common)
+            if tc["fp64"]["reached"] and tc[f"mixed_{args.mixed}"]["reached"]:
+                tc["speedup_mixed_vs_fp64"] = (tc["fp64"]["time_s"] /
+                                               tc[f"mixed_{args.mixed}"]["time_s"])
+            ttt["common_tol"] = tc
+        log(f"time to tol: fp64 {ttt['fp64']}, mixed {ttt[f'mixed_{args.mixed}']}")
+        sup_name = {"tall_100000x2000": "tall_cond10_100000x2000"}.get(args.workload)
+        if sup_name:
+            ttt["supplementary"] = time_to_tol_supplementary(
+                sup_name, args, dev, P, to_bf16_bits, make, WORKLOADS)
+        res["time_to_tol"] = ttt
+
         # Algorithm 3: flexible AB-GMRES with ROR-BK inner iterations (FP64),
         # against plain ROR-BK run for the same number of inner iterations
         outer, inner = 30, 20
@@ -243,13 +335,9 @@ def main():
         torch.cuda.synchronize()
         res["initial_solution"] = {"ms": (time.perf_counter() - t0) * 1e3, "coefficient": coef,
                                    "rrn_x0": float(s64.residual(b, x0i)[2])}
-        if not csr:
+        if soth is not None:
             # the other 16-/32-bit storage beside the one timed as `value`
             other = "bf16" if args.mixed == "f32" else "f32"
-            Aoth = Abf if other == "bf16" else A32
-            soth = P.Solver(Aoth, br, lam, A64=A64)
-            soth.set_refine(args.inner, 1e-4)
-            run(soth, True, args.warmup)
             xo, io, to = run(soth, True, K, profile=True)
             po = soth.profile()
             eo = 2 if other == "bf16" else 4
@@ -280,26 +368,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
-        t0 = time.time()
-        Wo = O.proposal(O.cosine_rowsums(oracle_A, br), n)[1]     # the oracle's own proposal
-        t_prop = time.time() - t0
-        probe = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=3, W=Wo,
-                        record=False)
-        per = max(probe["t_iter_s"] / 3, 1e-4)
-        N = int(min(2000, max(10, args.cpu_seconds / per)))
-        log(f"oracle: setup {probe['t_setup_s']:.2f}s, {per * 1e3:.1f} ms/iter; sample {N} iters")
-        ref = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N, W=Wo, record=False)
-        per = ref["t_iter_s"] / max(ref["iters"], 1)
-        # the oracle follows the FP64 solve's trajectory, so it needs the same
-        # number of iterations to the tolerance (or the cap)
-        need = i64["iters"] if not args.skip_extra else im["iters"]
-        cpu = {"value": per * need, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": (f"FP64 oracle setup once (proposal {t_prop:.2f}s + block factors "
-                          f"{ref['t_setup_s']:.2f}s, not counted) + "
-                          f"{ref['iters']} outer iterations on the full {m}x{n} system; "
-                          f"per-iteration time x {need} iterations (the FP64 solve's count "
-                          f"to the tolerance or the cap)"),
-               "iters_per_s": 1.0 / per}
+        need = i64["iters"] if i64 is not None else im["iters"]
+        ttt = res.get("time_to_tol", {})
+        cpu, ref, N = cpu_baseline(O, oracle_A, br, lam, bh, seed, tol, n, need, ttt, args)
         # GPU solves against the oracle over the same N iterations
         xg64, _, _ = run(s64, False, N)
         xgm, _, _ = run(smix, True, N)
@@ -325,10 +396,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "nnz": nnz, "block_rows": br,
                    "lambda": lam, "cond": WORKLOADS[args.workload].get("cond"), "tol": tol,
-                   "cap_iters": K,
+                   "cap_iters": cap, "timed_iters": K,
                    "mixed": f"{args.mixed} storage inner passes, FP64 refinement every "
                             f"{args.inner} inner iterations",
                    "parallelism": "single GPU"},
+        "value_is": (f"seconds of the mixed solve over the timed region of --steps {K} outer "
+                     f"iterations (stops earlier only at the tolerance); time to the "
+                     f"tolerance or the cap is under time_to_tol"),
         "reached_tol": bool(im["converged"]),
         "iters": im["iters"],
         "rrn_at_end": im["rrn"],
@@ -338,6 +412,223 @@ def main():
         "cpu_baseline": cpu,
     }
     out.update(res)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_tol_supplementary(name, args, dev, P, to_bf16_bits, make, WORKLOADS):
+    """Mixed (FP32 and BF16 storage) and FP64 solves to the tolerance on the
+    labelled supplementary system; the oracle's iteration count from its
+    golden file beside the GPU's."""
+    import torch
+    t0 = time.time()
+    w = make(name)
+    log(f"generated supplementary {name} in {time.time() - t0:.1f}s")
+    A64h = w["A"]
+    m, n = A64h.shape
+    A64 = torch.from_numpy(A64h).to(dev)
+    A32 = A64.float()
+    Abf = torch.from_numpy(to_bf16_bits(A64h).view(np.int16)).view(torch.bfloat16).to(dev)
+    b = torch.from_numpy(w["b"]).to(dev)
+    br, lam, tol, seed, cap = w["block_rows"], w["lam"], w["tol"], w["seed"], w["max_iters"]
+    out = {"workload": name, "label": "supplementary: same shape, blocks, lambda and generator "
+                                      "as the tall workload at cond 10",
+           "m": m, "n": n, "cond": WORKLOADS[name]["cond"], "block_rows": br, "lambda": lam,
+           "tol": tol, "cap_iters": cap}
+    sols = {"fp64": (P.Solver(A64, br, lam), False),
+            "mixed_f32": (P.Solver(A32, br, lam, A64=A64), True),
+            "mixed_bf16": (P.Solver(Abf, br, lam, A64=A64), True)}
+    xs = w["xstar"]
+    for key, (sol, refine) in sols.items():
+        if refine:
+            sol.set_refine(args.inner, 1e-4)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        sol.solve(b, x, seed=seed, tol=0.0, max_iters=max(args.warmup, 1), refine=refine)
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = sol.solve(b, x, seed=seed, tol=tol, max_iters=cap, refine=refine)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        xh = x.cpu().numpy()
+        out[key] = {"reached": bool(info["converged"]), "iters": info["iters"], "time_s": dt,
+                    "rrn": info["rrn"], "n_refine": info["n_refine"],
+                    "rrn_of_returned_x_fp64": float(sols["fp64"][0].residual(b, x)[2]),
+                    "rel_err_to_xstar": float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))}
+        log(f"supplementary {key}: {dt:.3f}s, {info['iters']} iters, rrn {info['rrn']:.3e}, "
+            f"reached {info['converged']}")
+    for key in ("mixed_f32", "mixed_bf16"):
+        if out["fp64"]["reached"] and out[key]["reached"]:
+            out[key]["speedup_vs_fp64"] = out["fp64"]["time_s"] / out[key]["time_s"]
+    g = read_golden(os.path.join(ROOT, "tests", "golden", name + ".txt"))
+    if g:
+        out["oracle"] = {"iters": int(g["iters"][0]), "converged": bool(int(g["converged"][0])),
+                         "rrn": float(g["rrn"][0]),
+                         "source": f"tests/golden/{name}.txt (FP64 oracle run)"}
+        idx = np.array([int(v) for v in g["x_idx"]])
+        val = np.array([float(v) for v in g["x_val"]])
+        sol, _ = sols["fp64"]
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        x, info = sol.solve(b, x, seed=seed, tol=tol, max_iters=cap)
+        out["oracle"]["fp64_sampled_x_rel_err"] = float(
+            np.linalg.norm(x.cpu().numpy()[idx] - val) / np.linalg.norm(val))
+    for sol, _ in sols.values():
+        sol.close()
+    return out
+
+
+def cpu_baseline(O, oracle_A, br, lam, bh, seed, tol, n, need, ttt, args):
+    """The FP64 oracle on the host: its own proposal once, then three runs of
+    a bounded number of outer iterations on all threads (median per-iteration
+    time) and one shorter run on one thread, scaled to the iterations the GPU
+    FP64 solve ran (and to its iterations to the tolerance or the cap)."""
+    threads = O.num_threads()
+    t0 = time.time()
+    Wo = O.proposal(O.cosine_rowsums(oracle_A, br), n)[1]     # the oracle's own proposal
+    t_prop = time.time() - t0
+    probe = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=3, W=Wo, record=False)
+    per = max(probe["t_iter_s"] / 3, 1e-4)
+    N = int(min(2000, max(10, args.cpu_seconds / 3 / per)))
+    log(f"oracle: setup {probe['t_setup_s']:.2f}s, {per * 1e3:.1f} ms/iter; 3 runs of {N} iters")
+    pers = []
+    ref = None
+    for _ in range(3):
+        ref = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N, W=Wo, record=False)
+        pers.append(ref["t_iter_s"] / max(ref["iters"], 1))
+    per = float(np.median(pers))
+    # one thread: a shorter run (about a quarter of the sample's CPU time)
+    O.set_num_threads(1)
+    try:
+        p1 = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=1, W=Wo, record=False)
+        N1 = int(min(500, max(2, args.cpu_seconds / 4 / max(p1["t_iter_s"], 1e-4))))
+        r1 = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N1, W=Wo, record=False)
+    finally:
+        O.set_num_threads(threads)
+    per1 = r1["t_iter_s"] / max(r1["iters"], 1)
+    log(f"oracle: {per * 1e3:.1f} ms/iter on {threads} threads, {per1 * 1e3:.1f} on 1")
+    cpu = {"value": per * need, "unit": "s", "cores": threads, "kind": "oracle",
+           "sample": (f"FP64 oracle: its own proposal once ({t_prop:.2f}s) and block factors "
+                      f"({ref['t_setup_s']:.2f}s), not counted; 3 runs of {N} outer iterations "
+                      f"on the full system, median per-iteration time x {need} iterations (the "
+                      f"GPU FP64 solve's count in the timed region)"),
+           "iters_per_s": 1.0 / per,
+           "per_iter_s_runs": pers,
+           "one_thread": {"per_iter_s": per1, "iters": r1["iters"],
+                          "setup_s": r1["t_setup_s"], "iters_per_s": 1.0 / per1},
+           "host_cpu": host_cpu()}
+    if ttt.get("fp64"):
+        cpu["time_to_tol_s"] = per * ttt["fp64"]["iters"]
+        cpu["time_to_tol_note"] = (f"median per-iteration time x {ttt['fp64']['iters']} "
+                                   f"iterations (the GPU FP64 solve under the stop rule)")
+    sup = ttt.get("supplementary", {})
+    if sup.get("oracle"):
+        cpu["supplementary_time_to_tol_s"] = per * sup["oracle"]["iters"]
+    return cpu, ref, N
+
+
+def bench_diff(args, dev):
+    """Differentiation workload: FP32 forward of a fixed number of iterations
+    with x checkpointed every c iterations, then the backward (greedy sets
+    recomputed from the checkpoints) to dL/db and dL/dx0 of
+    L = ||x_K - x_t||^2; the recorded forward's backward alone gives the
+    recomputation's share.  Errors against the FP64 oracle's adjoint on the
+    GPU's recorded selections (FP64 GPU adjoint to 1e-10, FP32 to 1e-3)."""
+    import torch
+    import paper_2510_02156_amd as P
+    from workloads import make
+    w = make("diff_20000x1000")
+    A32h, A64h = w["A32"], w["A"]
+    m, n = A64h.shape
+    br, lam, seed, iters, c = (w["block_rows"], w["lam"], w["seed"], w["max_iters"],
+                               w["checkpoint_every"])
+    A32 = torch.from_numpy(A32h).to(dev)
+    A64 = torch.from_numpy(A64h).to(dev)
+    b32 = torch.from_numpy(w["b"].astype(np.float32)).to(dev)
+    b64 = torch.from_numpy(w["b"]).to(dev)
+    xt = w["xt"]
+    s32 = P.Solver(A32, br, lam)
+    s64 = P.Solver(A64, br, lam)
+
+    def sync_time(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    def fwd(sol, bb, dt, **kw):
+        x = torch.zeros(n, dtype=dt, device=dev)
+        return sol.solve(bb, x, seed=seed, tol=0.0, max_iters=iters, **kw)[0]
+
+    # warm-up of every path
+    for _ in range(2):
+        x = fwd(s32, b32, torch.float32, checkpoint_every=c)
+        s32.backward((2 * (x - torch.from_numpy(xt).to(dev, torch.float32))).contiguous())
+    K = max(1, min(args.steps, 5))   # repeated forward + backward runs, median reported
+    t_f, t_b, t_fr, t_br = [], [], [], []
+    for _ in range(K):
+        x, dt = sync_time(lambda: fwd(s32, b32, torch.float32, checkpoint_every=c))
+        t_f.append(dt)
+        g = (2 * (x - torch.from_numpy(xt).to(dev, torch.float32))).contiguous()
+        (gb, gx0), dt = sync_time(lambda: s32.backward(g))
+        t_b.append(dt)
+        x, dt = sync_time(lambda: fwd(s32, b32, torch.float32, record=True))
+        t_fr.append(dt)
+        (gbr, gx0r), dt = sync_time(lambda: s32.backward(g))
+        t_br.append(dt)
+    rec = s32.record()
+    # FP64 GPU adjoint on the same selections (replayed)
+    s64.set_replay(rec["tau"], rec["I"], iters)
+    x64 = torch.zeros(n, dtype=torch.float64, device=dev)
+    s64.solve(b64, x64, seed=0, tol=0.0, max_iters=iters, replay=True, record=True)
+    g64d = torch.from_numpy(2 * (x64.cpu().numpy() - xt)).to(dev)
+    gb64, gx064 = s64.backward(g64d)
+    med = lambda v: float(np.median(v))   # noqa: E731
+    tf, tb, tfr, tbr = med(t_f), med(t_b), med(t_fr), med(t_br)
+    cpu, e32, e64 = None, None, None
+    if not args.no_cpu_baseline:
+        # the FP64 oracle on the host: the forward replaying the GPU's
+        # selections, then its adjoint; its gradients are the FP64 reference
+        import oracle as O
+        t0 = time.time()
+        ref = O.solve(A64h, br, lam, w["b"], seed=0, max_iters=iters, replay_tau=rec["tau"],
+                      replay_I=rec["I"], record=False)
+        t_of = time.time() - t0
+        t0 = time.time()
+        rb, rx0 = O.backward(A64h, br, lam, rec["tau"], rec["I"], iters, False,
+                             2 * (ref["x"] - xt))
+        t_ob = time.time() - t0
+        cpu = {"value": t_of + t_ob, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": (f"FP64 oracle: the {iters}-iteration forward replaying the GPU's "
+                          f"selections ({t_of:.2f}s, setup included) and its adjoint "
+                          f"({t_ob:.2f}s); the whole workload, not a sample"),
+               "host_cpu": host_cpu()}
+        gbh, gxh = gb.double().cpu().numpy(), gx0.double().cpu().numpy()
+        e32 = {"dL_db": float(np.linalg.norm(gbh - rb) / np.linalg.norm(rb)),
+               "dL_dx0": float(np.linalg.norm(gxh - rx0) / np.linalg.norm(rx0)),
+               "x_K": float(np.linalg.norm(x.double().cpu().numpy() - ref["x"]) /
+                            np.linalg.norm(ref["x"]))}
+        rb2, rx02 = O.backward(A64h, br, lam, rec["tau"], rec["I"], iters, False,
+                               2 * (x64.cpu().numpy() - xt))
+        e64 = {"dL_db": float(np.linalg.norm(gb64.cpu().numpy() - rb2) / np.linalg.norm(rb2)),
+               "dL_dx0": float(np.linalg.norm(gx064.cpu().numpy() - rx02) / np.linalg.norm(rx02)),
+               "x_K": float(np.linalg.norm(x64.cpu().numpy() - ref["x"]) /
+                            np.linalg.norm(ref["x"]))}
+    out = {
+        "metric": "differentiation: forward + backward time of the recorded iterations (s)",
+        "value": tf + tb, "unit": "s", "n_gpus": 1, "steps": K, "warmup": 2,
+        "ms_per_step": (tf + tb) / iters * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "diff_20000x1000", "m": m, "n": n, "block_rows": br,
+                   "lambda": lam, "iters": iters, "checkpoint_every": c,
+                   "parallelism": "single GPU"},
+        "forward_checkpointed_s": tf, "backward_checkpointed_s": tb,
+        "forward_recorded_s": tfr, "backward_recorded_s": tbr,
+        "recompute_share_of_backward": (tb - tbr) / tb if tb > 0 else None,
+        "error_fp32_vs_fp64_oracle": e32, "error_fp64_vs_oracle": e64,
+        "runs": K, "cpu_baseline": cpu,
+    }
+    log(f"diff: forward {tf * 1e3:.2f} ms, backward {tb * 1e3:.2f} ms (recorded: "
+        f"{tfr * 1e3:.2f} / {tbr * 1e3:.2f} ms); errors {e32} {e64}")
     print(json.dumps(out), flush=True)
 
 

@@ -75,6 +75,8 @@ def lib():
                                    C.c_int32, P, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_fabgmres.restype = C.c_int
         L.orc_fabgmres.argtypes = [P, C.c_int64, C.c_double, P, P, C.c_uint64, C.c_double,
                                    C.c_int64, C.c_int64, C.c_double, P, P, P, P, P]
@@ -342,8 +344,14 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(t: int) -> None:
+    """Threads of the oracle's parallel loops (timing only; results do not
+    depend on it)."""
+    lib().orc_set_num_threads(int(t))
+
+
 __all__ = ["ORC_OK", "ORC_ERR_ARG", "ORC_ERR_OOM", "ORC_ERR_NOT_SPD", "ORC_ERR_NONFINITE",
            "Matrix", "OracleError", "num_blocks", "partition", "cosine_rowsums",
            "proposal", "splitmix64_word", "sample", "sample_many", "cholesky",
            "chol_solve", "block_factor", "apply_block", "residual", "topk", "solve", "backward",
-           "initial_solution", "fabgmres", "num_threads", "lib"]
+           "initial_solution", "fabgmres", "num_threads", "set_num_threads", "lib"]

@@ -780,10 +780,14 @@ done:
     return rc;
 }
 
-/* Number of threads OpenMP will use (reported with the CPU timings). */
+/* Number of threads OpenMP will use (reported with the CPU timings), and a
+ * way to change it for a timing run (results never depend on it: every sum
+ * is sequential in index order). */
 #ifdef _OPENMP
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int t) { if (t > 0) omp_set_num_threads(t); }
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_num_threads(int t) { (void)t; }
 #endif
