@@ -233,6 +233,36 @@ int ror_bk_residual(rorbk_handle h, const void *b, const void *x, void *r,
                     double *block_norm2, int32_t vec_f32,
                     int32_t use_f64_master, double *rrn_host);
 
+/* Size of the static scratch array behind ror_bk_residual_noalloc (16 MiB,
+ * one copy on each GPU the library runs on, held until the process ends). */
+#define RORBK_NOALLOC_SCRATCH_BYTES 16777216
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual pass of ror_bk_residual without a handle and without any
+ * allocation.  It runs the same kernels on the matrix described by A
+ * (dense or CSR, not validated on the device: CSR arrays must be well formed)
+ * partitioned as ror_bk_partition(A->m, block_rows) does, and enqueues on
+ * `stream` (a hipStream_t or NULL) without synchronising:
+ *   r = b - A x (device, written), block_norm2 (device, k doubles, may be
+ *   NULL), *rrn = ||r|| / ||b|| (device, one double, may be NULL; NaN or Inf
+ *   when the residual is not finite, as no status can be returned without a
+ *   synchronisation).
+ * b, x, r are of the vector type vec_f32 selects (0: double, reading A->values
+ * for F64 storage, else A->values_f64; 1: float, F32 or BF16 storage).
+ * Workspace: the static array (RORBK_NOALLOC_SCRATCH_BYTES) holds 1024 bytes
+ * of control data, then 8 bytes per selection chunk, 8 per block when
+ * block_norm2 is NULL and 8 x m x ceil(n / 2048) (dense; 8 x m for CSR) for
+ * the partial products, each part rounded up to 256 bytes; larger problems
+ * return RORBK_ERR_UNSUPPORTED before any device work.  Calls no hipMalloc,
+ * hipFree or allocating routine.  Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Blocks of more than RORBK_MAX_BIG_BLOCK_ROWS rows: RORBK_ERR_UNSUPPORTED. */
+int ror_bk_residual_noalloc(const rorbk_matrix *A, int64_t block_rows, const void *b,
+                            const void *x, void *r, double *block_norm2, double *rrn,
+                            int32_t vec_f32, void *stream);
+
 /* What the last solve on the handle recorded of Algorithm 1 (host buffers,
  * caller-owned, each may be NULL): tau (3*iters int32, the inner loop's
  * sampled blocks), the greedy sets I (iters*K int32, rows ascending; only

@@ -30,12 +30,13 @@ RORBK_DENSE, RORBK_CSR = 0, 1
 RORBK_F64, RORBK_F32, RORBK_BF16 = 0, 1, 2
 RORBK_REFINE, RORBK_RECORD, RORBK_REPLAY, RORBK_CHECKPOINT = 1, 2, 4, 8
 RORBK_PROFILE = 16
+RORBK_NOALLOC_SCRATCH_BYTES = 16777216
 
 EXPORTS = [
     "ror_bk_partition", "ror_bk_setup", "ror_bk_solve", "ror_bk_backward", "ror_bk_destroy",
     "ror_bk_get_sizes", "ror_bk_get_setup", "ror_bk_set_proposal",
     "ror_bk_get_block_inverse", "ror_bk_get_form", "ror_bk_sample", "ror_bk_topk", "ror_bk_residual",
-    "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
+    "ror_bk_residual_noalloc", "ror_bk_get_record", "ror_bk_set_replay", "ror_bk_set_refine",
     "ror_bk_get_profile", "ror_bk_initial_solution", "ror_bk_fabgmres", "ror_bk_error_string",
     "ror_bk_last_error_message",
 ]
@@ -96,6 +97,8 @@ def lib():
             "ror_bk_sample": (C.c_int, [P, C.c_uint64, I64, I64, P]),
             "ror_bk_topk": (C.c_int, [P, P, I32, P]),
             "ror_bk_residual": (C.c_int, [P, P, P, P, P, I32, I32, P]),
+            "ror_bk_residual_noalloc": (C.c_int, [C.POINTER(rorbk_matrix), I64, P, P, P, P, P,
+                                                  I32, P]),
             "ror_bk_get_record": (C.c_int, [P, P, P, P, P]),
             "ror_bk_set_replay": (C.c_int, [P, P, P, I64]),
             "ror_bk_set_refine": (C.c_int, [P, I64, D]),
@@ -168,6 +171,16 @@ def ror_bk_setup(A=None, block_rows: int = 1, lam: float = 0.0, stream=None, *,
     (row stride = ld).  CSR: ``rowptr`` (int64), ``colidx`` (int32),
     ``values`` and ``shape``.  ``A64``: optional FP64 master copy (same layout).
     Returns (handle, descriptor); keep the tensors alive while the handle lives."""
+    d = matrix_descriptor(A, rowptr=rowptr, colidx=colidx, values=values, shape=shape, A64=A64)
+    h = C.c_void_p()
+    _check(lib().ror_bk_setup(C.byref(d), int(block_rows), float(lam), _stream_ptr(stream),
+                              C.byref(h)), "ror_bk_setup")
+    return h, d
+
+
+def matrix_descriptor(A=None, *, rowptr=None, colidx=None, values=None, shape=None, A64=None):
+    """rorbk_matrix for a dense 2-D tensor ``A`` (unit column stride) or CSR
+    arrays; the tensors must outlive every use of the descriptor."""
     d = rorbk_matrix()
     if A is not None:
         if A.dim() != 2 or A.stride(1) != 1:
@@ -188,10 +201,7 @@ def ror_bk_setup(A=None, block_rows: int = 1, lam: float = 0.0, stream=None, *,
         d.colidx = colidx.data_ptr()
         d.nnz = values.numel()
     d.values_f64 = A64.data_ptr() if A64 is not None else None
-    h = C.c_void_p()
-    _check(lib().ror_bk_setup(C.byref(d), int(block_rows), float(lam), _stream_ptr(stream),
-                              C.byref(h)), "ror_bk_setup")
-    return h, d
+    return d
 
 
 def ror_bk_solve(h, b, x, seed: int, tol: float, max_iters: int, start_iter: int = 0,
@@ -266,6 +276,17 @@ def ror_bk_residual(h, b, x, r, block_norm2=None, use_f64_master: bool = False) 
                                  vec_f32, int(bool(use_f64_master)), C.byref(rrn)),
            "ror_bk_residual")
     return rrn.value
+
+
+def ror_bk_residual_noalloc(desc, block_rows: int, b, x, r, block_norm2=None, rrn=None,
+                            stream=None):
+    """Enqueue the handle-free, allocation-free residual pass (device outputs
+    r, block_norm2, rrn; nothing is synchronised or allocated here)."""
+    vec_f32 = 1 if str(b.dtype) == "torch.float32" else 0
+    _check(lib().ror_bk_residual_noalloc(C.byref(desc), int(block_rows), _dev_ptr(b), _dev_ptr(x),
+                                         _dev_ptr(r), _dev_ptr(block_norm2), _dev_ptr(rrn),
+                                         vec_f32, _stream_ptr(stream)),
+           "ror_bk_residual_noalloc")
 
 
 def ror_bk_get_record(h, K: int):

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1448,3 +1449,165 @@ int ror_bk_backward(rorbk_handle h, const void *grad_x, void *grad_b, void *grad
 }
 
 }  // extern "C"
+
+// ============================================ residual pass without allocation
+// ror_bk_residual_noalloc: the residual pass of ror_bk_residual for callers
+// that cannot allocate device memory.  Its workspace (control block, the
+// selection counter, norms, the residual's partial products) lives in the
+// file-scope array below, one copy per GPU, held until the process ends.  Host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (looked up on the first call on that device); the
+// array's own name is a host-side stand-in and is never passed to a kernel.
+static __device__ __align__(256) unsigned char scratch[RORBK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t NOALLOC_BYTES = RORBK_NOALLOC_SCRATCH_BYTES;
+constexpr int NOALLOC_MAX_DEV = 64;
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+int g_noalloc_ncu[NOALLOC_MAX_DEV] = {};
+
+// The current device's copy of the scratch array and its compute-unit count.
+int noalloc_scratch(void **ptr, int *ncu) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEV)
+        return fail(RORBK_ERR_UNSUPPORTED, "device %d beyond the %d devices supported", dev,
+                    NOALLOC_MAX_DEV);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RORBK_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        g_noalloc_ncu[dev] = n;
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    *ncu = g_noalloc_ncu[dev];
+    return RORBK_OK;
+}
+
+__global__ void k_rrn_out(const Ctrl *__restrict__ c, double *__restrict__ rrn) {
+    const double bn2 = c->bnorm2;
+    *rrn = bn2 > 0.0 ? sqrt(c->rnorm2 / bn2) : 0.0;
+}
+
+size_t round256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" int ror_bk_residual_noalloc(const rorbk_matrix *A, int64_t block_rows, const void *b,
+                                       const void *x, void *r, double *block_norm2, double *rrn,
+                                       int32_t vec_f32, void *stream) {
+    g_msg[0] = 0;
+    // ---- host-side checks (nothing touches the device before they pass)
+    if (!A || !b || !x || !r) return fail(RORBK_ERR_INVALID_ARG, "NULL argument");
+    if (A->format != RORBK_DENSE && A->format != RORBK_CSR)
+        return fail(RORBK_ERR_INVALID_ARG, "unknown format %d", A->format);
+    if (A->dtype != RORBK_F64 && A->dtype != RORBK_F32 && A->dtype != RORBK_BF16)
+        return fail(RORBK_ERR_INVALID_ARG, "unknown dtype %d", A->dtype);
+    if (A->m < 1 || A->n < 1) return fail(RORBK_ERR_INVALID_ARG, "empty matrix");
+    if (A->m > INT32_MAX || A->n > INT32_MAX)
+        return fail(RORBK_ERR_UNSUPPORTED, "dimensions above 2^31 are not supported");
+    const bool dense = A->format == RORBK_DENSE;
+    if (dense && A->ld < A->n)
+        return fail(RORBK_ERR_INVALID_ARG, "ld %lld < n %lld", (long long)A->ld, (long long)A->n);
+    if (!dense) {
+        if (!A->rowptr || A->nnz < 0)
+            return fail(RORBK_ERR_INVALID_ARG, "CSR needs rowptr and nnz >= 0");
+        if (A->dtype == RORBK_BF16) return fail(RORBK_ERR_UNSUPPORTED, "BF16 storage is dense only");
+        if (A->nnz > 0 && (!A->colidx || !A->values))
+            return fail(RORBK_ERR_INVALID_ARG, "CSR with nnz > 0 needs colidx and values");
+    }
+    if (block_rows < 1 || block_rows > A->m)
+        return fail(RORBK_ERR_INVALID_ARG, "block_rows %lld outside [1, m=%lld]",
+                    (long long)block_rows, (long long)A->m);
+    const int vec = vec_f32 ? VEC_F32 : VEC_F64;
+    const void *Am = A->values;
+    int dt = A->dtype;
+    if (vec == VEC_F64 && dt != RORBK_F64) {
+        if (!A->values_f64) return fail(RORBK_ERR_INVALID_ARG, "double vectors need values_f64");
+        Am = A->values_f64;
+        dt = RORBK_F64;
+    }
+    if (vec == VEC_F32 && dt == RORBK_F64)
+        return fail(RORBK_ERR_INVALID_ARG, "float vectors need F32 or BF16 storage");
+    if (!Am && !(!dense && A->nnz == 0)) return fail(RORBK_ERR_INVALID_ARG, "matrix values are NULL");
+
+    rorbk_handle_s hh;
+    memset(&hh, 0, sizeof(hh));
+    Layout &L = hh.L;
+    L.m = A->m;
+    L.n = A->n;
+    L.ld = dense ? A->ld : A->n;
+    L.nnz = A->nnz;
+    L.format = A->format;
+    L.dtype = A->dtype;
+    L.k = A->m / block_rows;
+    L.q = A->m / L.k;
+    L.rem = A->m - L.k * L.q;
+    L.K = L.q;
+    L.bmax = L.q + (L.rem > 0 ? 1 : 0);
+    if (L.bmax > RORBK_MAX_BIG_BLOCK_ROWS)
+        return fail(RORBK_ERR_UNSUPPORTED, "blocks of %lld rows exceed the supported %d",
+                    (long long)L.bmax, RORBK_MAX_BIG_BLOCK_ROWS);
+    L.nseg = dense ? (int32_t)((L.n + 2047) / 2048) : 1;
+    int64_t bpc = 4096 / L.bmax;
+    if (bpc > 256) bpc = 256;
+    if (bpc < 1) bpc = 1;
+    L.bpc = bpc;
+    L.nch_s = (int32_t)((L.k + bpc - 1) / bpc);
+    // scratch layout: control block, counter, norm scratch | chunk norms |
+    // block norms (unless the caller takes them) | partial products
+    const size_t off_cn = 1024;
+    const size_t off_bn = off_cn + round256(8 * (size_t)L.nch_s);
+    const size_t off_axp = off_bn + (block_norm2 ? 0 : round256(8 * (size_t)L.k));
+    const size_t need = off_axp + round256(8 * (size_t)L.nseg * (size_t)L.m);
+    if (need > NOALLOC_BYTES)
+        return fail(RORBK_ERR_UNSUPPORTED,
+                    "needs %zu bytes of scratch (8 x %d segments x %lld rows of partial products "
+                    "plus norms), above the %zu bytes of the static array",
+                    need, L.nseg, (long long)L.m, NOALLOC_BYTES);
+
+    // ---- device work, enqueued on the caller's stream; no allocation
+    void *base = nullptr;
+    CHK(noalloc_scratch(&base, &hh.ncu));
+    char *sb = (char *)base;
+    hh.stream = (hipStream_t)stream;
+    hh.A = A->values;
+    hh.rowptr = A->rowptr;
+    hh.colidx = A->colidx;
+    hh.d_ctrl = (Ctrl *)sb;
+    hh.d_selcnt = (uint32_t *)(sb + 256);
+    hh.d_red = (double *)(sb + 512);
+    hh.d_cn = (double *)(sb + off_cn);
+    hh.d_bn = block_norm2 ? block_norm2 : (double *)(sb + off_bn);
+    hh.d_axp = (double *)(sb + off_axp);
+    const int al = (dense && aligned16(Am, L.ld, dtype_size(dt))) ? 1 : 0;
+    hipStream_t s = hh.stream;
+    // the counter must start at zero (a fill kernel, not a memset node)
+    HIPCHK(launch_fill_zero(hh.d_selcnt, 4, s));
+    HIPCHK(launch_norm2(b, vec, L.m, hh.d_red, hh.d_red, s));
+    HIPCHK(launch_init_ctrl(hh.d_ctrl, 0.0, hh.d_red, s));
+    HIPCHK(residual(&hh, Am, dt, al, vec, x, hh.d_axp));
+    SelectArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.vec = vec;
+    sa.b = b;
+    sa.axp = hh.d_axp;
+    sa.nseg = L.nseg;
+    sa.r = r;
+    sa.skip_topk = 1;
+    HIPCHK(launch_select(&hh, sa, s));
+    if (rrn) {
+        hipLaunchKernelGGL(k_rrn_out, dim3(1), dim3(1), 0, s, (const Ctrl *)hh.d_ctrl, rrn);
+        HIPCHK(hipGetLastError());
+    }
+    return RORBK_OK;
+}

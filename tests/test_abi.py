@@ -167,3 +167,43 @@ def test_product_path_does_not_reach_the_oracle():
             with open(os.path.join(dirpath, fn)) as f:
                 text = f.read()
             assert "oracle" not in text.lower(), os.path.join(dirpath, fn)
+
+
+def test_noalloc_residual_refuses_oversized_problems_before_any_device_call():
+    """ror_bk_residual_noalloc checks its arguments and the size of its static
+    scratch on the host: a problem whose partial products exceed the array
+    (RORBK_NOALLOC_SCRATCH_BYTES) is refused with RORBK_ERR_UNSUPPORTED, and
+    bad arguments with RORBK_ERR_INVALID_ARG, before anything reaches a
+    device (the pointers below are never dereferenced)."""
+    from paper_2510_02156_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("librorbk.so not built")
+    L = binding.lib()
+    fake = C.c_void_p(0x1000)
+    cap = binding.RORBK_NOALLOC_SCRATCH_BYTES
+    m = cap // 8 + 1          # one segment of partial products alone exceeds the array
+    A = binding.rorbk_matrix(format=binding.RORBK_DENSE, dtype=binding.RORBK_F64, m=m, n=100,
+                             ld=100, values=fake, rowptr=None, colidx=None, nnz=0,
+                             values_f64=None)
+    rc = L.ror_bk_residual_noalloc(C.byref(A), 64, fake, fake, fake, None, None, 0, None)
+    assert rc == binding.RORBK_ERR_UNSUPPORTED
+    assert b"scratch" in L.ror_bk_last_error_message()
+    # several column segments multiply the need: 3 segments of 1e6 rows
+    A.m, A.n, A.ld = 1000000, 5000, 5000
+    assert L.ror_bk_residual_noalloc(C.byref(A), 64, fake, fake, fake, None, None, 0,
+                                     None) == binding.RORBK_ERR_UNSUPPORTED
+    # argument errors
+    A.m, A.n, A.ld = 1000, 100, 100
+    assert L.ror_bk_residual_noalloc(C.byref(A), 0, fake, fake, fake, None, None, 0,
+                                     None) == binding.RORBK_ERR_INVALID_ARG
+    assert L.ror_bk_residual_noalloc(C.byref(A), 10, None, fake, fake, None, None, 0,
+                                     None) == binding.RORBK_ERR_INVALID_ARG
+    assert L.ror_bk_residual_noalloc(C.byref(A), 10, fake, fake, fake, None, None, 1,
+                                     None) == binding.RORBK_ERR_INVALID_ARG   # float vs F64
+    A.dtype = binding.RORBK_F32
+    assert L.ror_bk_residual_noalloc(C.byref(A), 10, fake, fake, fake, None, None, 0,
+                                     None) == binding.RORBK_ERR_INVALID_ARG   # no FP64 master
+    A.dtype = binding.RORBK_F64
+    A.m = 10000
+    assert L.ror_bk_residual_noalloc(C.byref(A), 2049, fake, fake, fake, None, None, 0,
+                                     None) == binding.RORBK_ERR_UNSUPPORTED   # block rows
