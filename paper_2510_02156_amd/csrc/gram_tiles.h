@@ -55,9 +55,9 @@ __device__ __forceinline__ void gram64_accumulate(const T *const (&pa)[4], const
                         xa[u][s2][h] = *reinterpret_cast<const uvec4 *>(pa[s2] + cc);
                         xb[u][s2][h] = same ? zu : *reinterpret_cast<const uvec4 *>(pb[s2] + cc);
                     } else {
-                        xa[u][s2][h] = (va[s2] && cc < wb) ? load_raw<T, AL>(pa[s2], cc, wb) : zu;
-                        xb[u][s2][h] =
-                            (!same && vb[s2] && cc < wb) ? load_raw<T, AL>(pb[s2], cc, wb) : zu;
+                        // rows are valid even where va / vb are false
+                        xa[u][s2][h] = load_raw_sel<T, AL>(pa[s2], cc, wb, va[s2], pa[s2], wa);
+                        xb[u][s2][h] = load_raw_sel<T, AL>(pb[s2], cc, wb, !same && vb[s2], pb[s2], wa);
                     }
                 }
             }

@@ -702,7 +702,7 @@ __global__ __launch_bounds__(BIG_T) void k_big_upd(BigP p) {
         const int i = r0 + g + G * u;
         const bool live = i < cnt;
         const int64_t row = live ? sel_row(p.cur, cst, i) : 0;
-        ua[u] = (live && col < c1) ? load_raw<T, AL>(A + row * p.ld, col, c1) : zero4;
+        ua[u] = load_raw_sel<T, AL>(A + row * p.ld, col, c1, live, A, c0);
         yv[u] = live ? p.y[i] : 0.0;
     }
     if (blockIdx.y == 0)
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(BIG_T) void k_big_apply(BigP p) {
         const int i = r0 + g + G * u;
         const bool live = i < ncnt;
         const int64_t row = live ? sel_row(p.nxt, nst, i) : 0;
-        un[u] = (live && col < c1) ? load_raw<T, AL>(A + row * p.ld, col, c1) : zero4;
+        un[u] = load_raw_sel<T, AL>(A + row * p.ld, col, c1, live, A, c0);
     }
     __shared__ V s_x[128];
     if (tid < 128) {
@@ -852,8 +852,8 @@ __global__ __launch_bounds__(256) void k_gram32(const T *__restrict__ A, int64_t
                 const int64_t cc = col + h * VW;
 #pragma unroll
                 for (int s2 = 0; s2 < 2; ++s2) {
-                    xa[u][s2][h] = (va[s2] && cc < wb) ? load_raw<T, AL>(pa[s2], cc, wb) : zu;
-                    xb[u][s2][h] = (!same && vb[s2] && cc < wb) ? load_raw<T, AL>(pb[s2], cc, wb) : zu;
+                    xa[u][s2][h] = load_raw_sel<T, AL>(pa[s2], cc, wb, va[s2], pa[s2], wa);
+                    xb[u][s2][h] = load_raw_sel<T, AL>(pb[s2], cc, wb, !same && vb[s2], pb[s2], wa);
                 }
             }
         }

@@ -104,8 +104,10 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int64_t col = c0 + (int64_t)v * VW;
-        ua[r] = (crow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, col, c1) : zero4;
-        un[r] = (nrow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, col, c1) : zero4;
+        ua[r] = load_raw_sel<T, AL>(A + (int64_t)(crow[r] >= 0 ? crow[r] : 0) * p.ld, col, c1,
+                                    crow[r] >= 0, A, c0);
+        un[r] = load_raw_sel<T, AL>(A + (int64_t)(nrow[r] >= 0 ? nrow[r] : 0) * p.ld, col, c1,
+                                    nrow[r] >= 0, A, c0);
     }
     for (int c = tid; c < wcols; c += NT) s_x[c] = x[c0 + c];
 
@@ -203,15 +205,19 @@ __global__ __launch_bounds__(STEP_T) void k_step_dense(StepP p) {
                 const int64_t coln = col + 128;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    ua2[r] = (crow[r] >= 0 && coln < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, coln, c1) : zero4;
-                    un2[r] = (nrow[r] >= 0 && coln < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, coln, c1) : zero4;
+                    ua2[r] = load_raw_sel<T, AL>(A + (int64_t)(crow[r] >= 0 ? crow[r] : 0) * p.ld, coln,
+                                                 c1, crow[r] >= 0, A, c0);
+                    un2[r] = load_raw_sel<T, AL>(A + (int64_t)(nrow[r] >= 0 ? nrow[r] : 0) * p.ld, coln,
+                                                 c1, nrow[r] >= 0, A, c0);
                 }
             }
         } else if (sub != c0) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                ua[r] = (crow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)crow[r] * p.ld, col, c1) : zero4;
-                un[r] = (nrow[r] >= 0 && col < c1) ? load_raw<T, AL>(A + (int64_t)nrow[r] * p.ld, col, c1) : zero4;
+                ua[r] = load_raw_sel<T, AL>(A + (int64_t)(crow[r] >= 0 ? crow[r] : 0) * p.ld, col, c1,
+                                            crow[r] >= 0, A, c0);
+                un[r] = load_raw_sel<T, AL>(A + (int64_t)(nrow[r] >= 0 ? nrow[r] : 0) * p.ld, col, c1,
+                                            nrow[r] >= 0, A, c0);
             }
         }
         if (upd) {

@@ -2,6 +2,7 @@
 // matrix (FP64, FP32 or BF16 storage): the one kernel that streams all of A
 // every outer iteration, and so the one bound by HBM bandwidth.
 #include "rorbk_device.h"
+#include "xgram.h"
 
 namespace rorbk {
 
@@ -19,14 +20,24 @@ constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 // combined by a fixed butterfly.  Each lane keeps its entries of x in
 // registers.  Rows past the end re-read the last row (in bounds) and discard
 // the result.  axp[seg][i] = partial (A x)_i; the selection kernel subtracts
-// the segment sum from b.  Grid: x = workgroups, y = segments.
+// the segment sum from b.  Grid: x = workgroups, y = segments.  The first
+// side.jobs workgroups of segment row 0 instead form the cross-Gram tiles of
+// the next iteration's sampled blocks (xgram.h): MFMA work on a few rows that
+// sits in cache, done while the pass streams A (those workgroups of the other
+// segment rows leave at once).
 template <typename T, typename V, bool AL, int ROWS, int SW>
 __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
                                                      const V *__restrict__ x,
                                                      double *__restrict__ axp,
-                                                     const Ctrl *__restrict__ ctrl) {
+                                                     const Ctrl *__restrict__ ctrl, XgSide side) {
     if (ctrl && ctrl->done) return;
+    if ((int)blockIdx.x < side.jobs) {
+        if (blockIdx.y == 0)
+            xgram_tile<T, AL>(A, ld, n, side.tau, side.ti, side.q, side.rem, side.bmax,
+                              (int)blockIdx.x, side.out);
+        return;
+    }
     constexpr int VW = Tr<T>::VW;
     constexpr int NVL = SW / (WAVE * VW);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -39,10 +50,11 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 #pragma unroll
         for (int e = 0; e < VW; ++e) xr[s][e] = (col + e < n) ? x[col + e] : (V)0;
     }
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
+    const int64_t bx = (int64_t)blockIdx.x - side.jobs;
+    const int64_t nwaves = (int64_t)(gridDim.x - side.jobs) * 4;
     const int64_t stride = nwaves * ROWS;
     const uvec4 zero = {0u, 0u, 0u, 0u};
-    for (int64_t i = ((int64_t)blockIdx.x * 4 + w) * ROWS; i < m; i += stride) {
+    for (int64_t i = (bx * 4 + w) * ROWS; i < m; i += stride) {
         uvec4 raw[ROWS][NVL];
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
@@ -50,7 +62,7 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 #pragma unroll
             for (int s = 0; s < NVL; ++s) {
                 const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
-                raw[rr][s] = (col < n) ? load_raw_nt<T, AL>(A + row * ld, col, n) : zero;
+                raw[rr][s] = load_raw_nt_sel<T, AL>(A + row * ld, col, n, true, A + row * ld, c0);
             }
         }
 #pragma unroll
@@ -71,7 +83,7 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 
 template <typename T, typename V, int ROWS, int SW>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
-                              const void *x, double *axp, hipStream_t s) {
+                              const void *x, double *axp, const XgSide &side, hipStream_t s) {
     static_assert(SW == SEG || SW == 512 || SW == 1024, "segment width");
     const Layout &L = h->L;
     // grid over all segments: 16 workgroups per CU for FP32 and FP64 rows of
@@ -91,14 +103,14 @@ static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligne
     }
     if (cap < 1) cap = 1;
     if (groups > cap) groups = cap;
-    dim3 grid((unsigned)groups, (unsigned)L.nseg);
+    dim3 grid((unsigned)(groups + side.jobs), (unsigned)L.nseg);
     if (aligned)
         hipLaunchKernelGGL((k_resid_dense<T, V, true, ROWS, SW>), grid, dim3(256), 0, s, (const T *)A,
-                           L.ld, L.m, L.n, (const V *)x, axp, (const Ctrl *)h->d_ctrl);
+                           L.ld, L.m, L.n, (const V *)x, axp, (const Ctrl *)h->d_ctrl, side);
     else
         hipLaunchKernelGGL((k_resid_dense<T, V, false, ROWS, SW>), grid, dim3(256), 0, s,
                            (const T *)A, L.ld, L.m, L.n, (const V *)x, axp,
-                           (const Ctrl *)h->d_ctrl);
+                           (const Ctrl *)h->d_ctrl, side);
     return hipGetLastError();
 }
 
@@ -106,23 +118,30 @@ static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligne
 // the loads one row takes (the segment width over 64 lanes x 16 bytes).
 hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt, int aligned,
                                  int vec, const void *x, double *axp, hipStream_t s) {
+    const XgSide none = {nullptr, 0, 0, 0, 0, 0, nullptr};
+    return launch_residual_dense_side(h, A, dt, aligned, vec, x, axp, none, s);
+}
+
+hipError_t launch_residual_dense_side(const rorbk_handle_s *h, const void *A, int dt, int aligned,
+                                      int vec, const void *x, double *axp, const XgSide &side,
+                                      hipStream_t s) {
     const int64_t n = h->L.n;
     if (vec == VEC_F64) {
         if (dt != RORBK_F64) return hipErrorInvalidValue;
-        if (n <= 512) return resid_typed<double, double, 4, 512>(h, A, aligned, x, axp, s);
-        if (n <= 1024) return resid_typed<double, double, 2, 1024>(h, A, aligned, x, axp, s);
+        if (n <= 512) return resid_typed<double, double, 4, 512>(h, A, aligned, x, axp, side, s);
+        if (n <= 1024) return resid_typed<double, double, 2, 1024>(h, A, aligned, x, axp, side, s);
         // the unaligned FP64 form needs twice the registers per row in flight
-        if (aligned) return resid_typed<double, double, 2, SEG>(h, A, aligned, x, axp, s);
-        return resid_typed<double, double, 1, SEG>(h, A, aligned, x, axp, s);
+        if (aligned) return resid_typed<double, double, 2, SEG>(h, A, aligned, x, axp, side, s);
+        return resid_typed<double, double, 1, SEG>(h, A, aligned, x, axp, side, s);
     }
     if (dt == RORBK_F32) {
-        if (n <= 512) return resid_typed<float, float, 8, 512>(h, A, aligned, x, axp, s);
-        if (n <= 1024) return resid_typed<float, float, 4, 1024>(h, A, aligned, x, axp, s);
-        return resid_typed<float, float, 2, SEG>(h, A, aligned, x, axp, s);
+        if (n <= 512) return resid_typed<float, float, 8, 512>(h, A, aligned, x, axp, side, s);
+        if (n <= 1024) return resid_typed<float, float, 4, 1024>(h, A, aligned, x, axp, side, s);
+        return resid_typed<float, float, 2, SEG>(h, A, aligned, x, axp, side, s);
     }
-    if (n <= 512) return resid_typed<bf16_t, float, 16, 512>(h, A, aligned, x, axp, s);
-    if (n <= 1024) return resid_typed<bf16_t, float, 8, 1024>(h, A, aligned, x, axp, s);
-    return resid_typed<bf16_t, float, 4, SEG>(h, A, aligned, x, axp, s);
+    if (n <= 512) return resid_typed<bf16_t, float, 16, 512>(h, A, aligned, x, axp, side, s);
+    if (n <= 1024) return resid_typed<bf16_t, float, 8, 1024>(h, A, aligned, x, axp, side, s);
+    return resid_typed<bf16_t, float, 4, SEG>(h, A, aligned, x, axp, side, s);
 }
 
 }  // namespace rorbk

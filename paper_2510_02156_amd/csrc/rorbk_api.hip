@@ -188,6 +188,10 @@ void destroy_all(rorbk_handle_s *h) {
     h->h_ctrl = nullptr;
     dfree(h->d_P[0]);
     dfree(h->d_P[1]);
+    dfree(h->d_P3);
+    dfree(h->d_XG);
+    dfree(h->d_z3);
+    dfree(h->d_fwdcnt);
     dfree(h->d_axp);
     dfree(h->d_r);
     dfree(h->d_bn);
@@ -299,6 +303,7 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
                    int64_t *ran, bool *stopped) {
     const Layout &L = h->L;
     hipStream_t s = h->stream;
+    const bool fused = h->fast3 != 0;
     int ping = 0;
     StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -309,14 +314,31 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     a.b = o.b;
     a.x = o.x;
     a.gb = nullptr;
-    // partial products of the first sampled step
-    a.cur.kind = -1;
-    a.ymode = 2;
-    a.nxt.kind = 0;
-    a.nxt.tau_index = 3 * it0;
-    a.Pout = h->d_P[ping ^ 1];
-    HIPCHK(step(h, a));
-    ping ^= 1;
+    FwdArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.A = o.A;
+    fa.dt = o.dt;
+    fa.aligned = o.aligned;
+    fa.vec = o.vec;
+    fa.b = o.b;
+    fa.x = o.x;
+    const int64_t xgs = 3 * L.bmax * L.bmax;   // one slot of cross-Grams
+    if (fused) {
+        // the first iteration's three-block products and cross-Grams
+        fa.I = nullptr;
+        fa.tau_index = 3 * it0;
+        HIPCHK(launch_fwd_greedy(h, fa, s));
+        HIPCHK(launch_xgram(h, o.A, o.dt, o.aligned, 3 * it0, h->d_XG + (it0 & 1) * xgs, s));
+    } else {
+        // partial products of the first sampled step
+        a.cur.kind = -1;
+        a.ymode = 2;
+        a.nxt.kind = 0;
+        a.nxt.tau_index = 3 * it0;
+        a.Pout = h->d_P[ping ^ 1];
+        HIPCHK(step(h, a));
+        ping ^= 1;
+    }
 
     const int64_t poll = 16;
     // residual-pass timings (iteration, ms); launches after the stopping
@@ -342,25 +364,40 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
             HIPCHK(hipMemcpyAsync(dst, o.x, (size_t)L.n * vec_size(o.vec),
                                   hipMemcpyDeviceToDevice, s));
         }
-        for (int l = 0; l < 3; ++l) {
-            a.cur.kind = 0;
-            a.cur.tau_index = 3 * it + l;
-            a.ymode = 0;
-            a.Pin = h->d_P[ping];
-            if (l < 2) {
-                a.nxt.kind = 0;
-                a.nxt.tau_index = 3 * it + l + 1;
-                a.Pout = h->d_P[ping ^ 1];
-            } else {
-                a.nxt.kind = -1;
-                a.Pout = nullptr;
+        if (fused) {
+            fa.tau_index = 3 * it;
+            fa.xg = h->d_XG + (it & 1) * xgs;
+            HIPCHK(launch_fwd_samp3(h, fa, s));
+        } else {
+            for (int l = 0; l < 3; ++l) {
+                a.cur.kind = 0;
+                a.cur.tau_index = 3 * it + l;
+                a.ymode = 0;
+                a.Pin = h->d_P[ping];
+                if (l < 2) {
+                    a.nxt.kind = 0;
+                    a.nxt.tau_index = 3 * it + l + 1;
+                    a.Pout = h->d_P[ping ^ 1];
+                } else {
+                    a.nxt.kind = -1;
+                    a.Pout = nullptr;
+                }
+                HIPCHK(step(h, a));
+                if (l < 2) ping ^= 1;
             }
-            HIPCHK(step(h, a));
-            if (l < 2) ping ^= 1;
         }
         const bool timed = h->profile && ((it - it0) % poll) == 0;
         if (timed) HIPCHK(hipEventRecord(h->evr[chunk & 1][0], s));
-        HIPCHK(residual(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_axp));
+        if (fused) {
+            // the next iteration's cross-Grams ride along in spare workgroups
+            XgSide side = {h->d_tau, 3 * (it + 1), L.q, L.rem, (int)L.bmax, 0,
+                           h->d_XG + ((it + 1) & 1) * xgs};
+            if (it + 1 < it1) side.jobs = fwd_xgram_jobs((int)L.bmax);
+            HIPCHK(launch_residual_dense_side(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_axp, side,
+                                              s));
+        } else {
+            HIPCHK(residual(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_axp));
+        }
         if (timed) {
             HIPCHK(hipEventRecord(h->evr[chunk & 1][1], s));
             timed_slot[chunk & 1] = 1;
@@ -391,21 +428,29 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
             HIPCHK(gram(h, o.A, o.dt, o.aligned, h->d_I, (int)L.K, h->d_G));
             HIPCHK(launch_chol_solve(h, h->d_G, (int)L.K, h->d_rI, nullptr, h->d_y, s));
         }
-        a.cur.kind = 1;
-        a.cur.count = (int32_t)L.K;
-        a.cur.idx = h->d_I;
-        a.ymode = 1;
-        a.ygiven = h->d_y;
-        if (it + 1 < it1) {
-            a.nxt.kind = 0;
-            a.nxt.tau_index = 3 * (it + 1);
-            a.Pout = h->d_P[ping ^ 1];
+        if (fused) {
+            // greedy update and the next iteration's three-block products
+            fa.I = h->d_I;
+            fa.y = h->d_y;
+            fa.tau_index = (it + 1 < it1) ? 3 * (it + 1) : -1;
+            HIPCHK(launch_fwd_greedy(h, fa, s));
         } else {
-            a.nxt.kind = -1;
-            a.Pout = nullptr;
+            a.cur.kind = 1;
+            a.cur.count = (int32_t)L.K;
+            a.cur.idx = h->d_I;
+            a.ymode = 1;
+            a.ygiven = h->d_y;
+            if (it + 1 < it1) {
+                a.nxt.kind = 0;
+                a.nxt.tau_index = 3 * (it + 1);
+                a.Pout = h->d_P[ping ^ 1];
+            } else {
+                a.nxt.kind = -1;
+                a.Pout = nullptr;
+            }
+            HIPCHK(step(h, a));
+            if (it + 1 < it1) ping ^= 1;
         }
-        HIPCHK(step(h, a));
-        if (it + 1 < it1) ping ^= 1;
         // poll the stop flag one chunk behind so the device never starves
         if (((it + 1 - it0) % poll) == 0 && it + 1 < it1) {
             const int slot = (int)(chunk & 1);
@@ -604,6 +649,29 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_ctrl, 1);
     ALLOC(h->d_P[0], (int64_t)L.nch_u * bmax);
     ALLOC(h->d_P[1], (int64_t)L.nch_u * bmax);
+    // dense row-form blocks of at most RORBK_FWD_MAX_BLOCK rows: fused forward
+    // steps (three-block partial products, two slots of cross-Grams)
+    h->fast3 = (L.format == RORBK_DENSE && !h->big && !h->col &&
+                bmax <= RORBK_FWD_MAX_BLOCK) ? 1 : 0;
+    if (h->fast3) {
+        // column slabs of the fused steps: sub-slabs of 64 (FP64 storage) or
+        // 128 columns; one per workgroup up to 64 of them, else several, for
+        // at most about 256 workgroups (x of a slab stays in LDS: <= 1024)
+        const int64_t swc = (L.dtype == RORBK_F64) ? 64 : 128;
+        const int64_t slabs = (L.n + swc - 1) / swc;
+        int64_t per = 1;
+        if (slabs > 64) {
+            per = (slabs + 255) / 256;
+            if (per < 2) per = 2;
+        }
+        if (per > 1024 / swc) per = 1024 / swc;
+        L.wf = per * swc;
+        L.nch_f = (int32_t)((L.n + L.wf - 1) / L.wf);
+        ALLOC(h->d_P3, (int64_t)L.nch_f * 3 * bmax);
+        ALLOC(h->d_XG, 2 * 3 * bmax * bmax);
+        ALLOC(h->d_z3, 3 * RORBK_FWD_MAX_BLOCK);
+        ALLOC(h->d_fwdcnt, 1);
+    }
     ALLOC(h->d_axp, (int64_t)L.nseg * L.m);
     {
         char *r = nullptr;
@@ -656,7 +724,9 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return fail(RORBK_ERR_OOM, "pinned allocation failed: %s", hipGetErrorString(e));
     }
     memset(h->h_ctrl, 0, 3 * sizeof(Ctrl));
-    if (hipMemsetAsync(h->d_selcnt, 0, sizeof(uint32_t), (hipStream_t)stream) != hipSuccess) {
+    if (hipMemsetAsync(h->d_selcnt, 0, sizeof(uint32_t), (hipStream_t)stream) != hipSuccess ||
+        (h->d_fwdcnt &&
+         hipMemsetAsync(h->d_fwdcnt, 0, sizeof(uint32_t), (hipStream_t)stream) != hipSuccess)) {
         destroy_all(h);
         delete h;
         return fail(RORBK_ERR_HIP, "clearing the selection counter failed");

@@ -115,15 +115,43 @@ __device__ __forceinline__ void load_vec_nt(const T *__restrict__ row, int64_t c
     }
 }
 
-// 16 raw bytes (VW elements) of a row at column c; elements at or past `lim`
-// read as zero.  ALIGNED as for load_vec.  Otherwise a full vector whose
-// address is 8-byte aligned (rows of 16- or 32-bit values whose stride is a
-// multiple of 8 bytes) is read as two 8-byte loads, anything else element by
-// element.
+// Elements of a raw 16-byte vector (VW elements from column c) at or past
+// `lim` set to zero, by selects (no branch).
+template <typename T>
+__device__ __forceinline__ uvec4 mask_raw(uvec4 w, int64_t c, int64_t lim) {
+    if constexpr (sizeof(T) == 8) {
+        const bool k1 = c + 1 < lim;
+        const bool k0 = c < lim;
+        w[0] = k0 ? w[0] : 0u;
+        w[1] = k0 ? w[1] : 0u;
+        w[2] = k1 ? w[2] : 0u;
+        w[3] = k1 ? w[3] : 0u;
+    } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = (c + e < lim) ? w[e] : 0u;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t lo = (c + 2 * e < lim) ? 0x0000ffffu : 0u;
+            const uint32_t hi = (c + 2 * e + 1 < lim) ? 0xffff0000u : 0u;
+            w[e] &= (lo | hi);
+        }
+    }
+    return w;
+}
+
+// 16 raw bytes (VW elements) of a row at column c (c < lim); elements at or
+// past `lim` read as zero.  ALIGNED (row start 16-byte aligned, row stride a
+// multiple of VW elements, c a multiple of VW): one 16-byte load, which stays
+// inside the row's stride even when it crosses lim (c < lim <= n <= stride),
+// and the tail masked by selects, so the code has no branch around the load.
+// Otherwise a full vector whose address is 8-byte aligned (rows of 16- or
+// 32-bit values whose stride is a multiple of 8 bytes) is read as two 8-byte
+// loads, anything else element by element.
 template <typename T, bool ALIGNED>
 __device__ __forceinline__ uvec4 load_raw(const T *__restrict__ row, int64_t c, int64_t lim) {
     constexpr int VW = Tr<T>::VW;
-    if (ALIGNED && c + VW <= lim) return *reinterpret_cast<const uvec4 *>(row + c);
+    if constexpr (ALIGNED) return mask_raw<T>(*reinterpret_cast<const uvec4 *>(row + c), c, lim);
     if constexpr (!ALIGNED && sizeof(T) < 8) {
         if (c + VW <= lim && (reinterpret_cast<uintptr_t>(row + c) & 7) == 0) {
             const uint2 lo = *reinterpret_cast<const uint2 *>(row + c);
@@ -157,10 +185,34 @@ __device__ __forceinline__ uvec4 load_raw(const T *__restrict__ row, int64_t c, 
 // once, not kept in the caches).
 template <typename T, bool ALIGNED>
 __device__ __forceinline__ uvec4 load_raw_nt(const T *__restrict__ row, int64_t c, int64_t lim) {
-    constexpr int VW = Tr<T>::VW;
-    if (ALIGNED && c + VW <= lim)
-        return __builtin_nontemporal_load(reinterpret_cast<const uvec4 *>(row + c));
+    if constexpr (ALIGNED)
+        return mask_raw<T>(__builtin_nontemporal_load(reinterpret_cast<const uvec4 *>(row + c)),
+                           c, lim);
     return load_raw<T, ALIGNED>(row, c, lim);
+}
+
+// load_raw of (row, c) when `ok` and c < lim, else zero, with no branch
+// around the load: otherwise the vector at (srow, sc) is read instead (any
+// vector known to lie inside the matrix, sc < lim) and dropped by a select.
+// (A load behind a lane-dependent branch makes the compiler wait for it to
+// land before the other lanes' zero may be written to the same registers,
+// which turns loads meant to overlap into a chain of memory round trips.)
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ uvec4 load_raw_sel(const T *__restrict__ row, int64_t c, int64_t lim,
+                                              bool ok, const T *__restrict__ srow, int64_t sc) {
+    const bool g = ok && c < lim;
+    const uvec4 w = load_raw<T, ALIGNED>(g ? row : srow, g ? c : sc, lim);
+    const uvec4 z = {0u, 0u, 0u, 0u};
+    return g ? w : z;
+}
+
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ uvec4 load_raw_nt_sel(const T *__restrict__ row, int64_t c, int64_t lim,
+                                                 bool ok, const T *__restrict__ srow, int64_t sc) {
+    const bool g = ok && c < lim;
+    const uvec4 w = load_raw_nt<T, ALIGNED>(g ? row : srow, g ? c : sc, lim);
+    const uvec4 z = {0u, 0u, 0u, 0u};
+    return g ? w : z;
 }
 
 template <typename T, typename V>
@@ -206,10 +258,8 @@ __device__ __forceinline__ void mfma_gram_tile(const T *__restrict__ X, int64_t 
             const int64_t col = c + (int64_t)u * 4 * E + (int64_t)g * E;
 #pragma unroll
             for (int h = 0; h < NL; ++h) {
-                const uvec4 z = {0u, 0u, 0u, 0u};
-                wa[u][h] = (ra >= 0 && col + h * VW < c1) ? load_raw<T, ALIGNED>(pa, col + h * VW, c1) : z;
-                wb[u][h] = (!same && rb >= 0 && col + h * VW < c1)
-                               ? load_raw<T, ALIGNED>(pb, col + h * VW, c1) : z;
+                wa[u][h] = load_raw_sel<T, ALIGNED>(pa, col + h * VW, c1, ra >= 0, X, c0);
+                wb[u][h] = load_raw_sel<T, ALIGNED>(pb, col + h * VW, c1, !same && rb >= 0, X, c0);
             }
         }
 #pragma unroll

@@ -32,6 +32,20 @@ struct Ctrl {
     double pad[2];
 };
 
+// Blocks of at most this many rows (dense, row form) run the fused forward
+// steps of k_fwd.hip: the three sampled updates in one launch.
+constexpr int RORBK_FWD_MAX_BLOCK = 65;
+
+// The cross-Gram tile jobs a residual launch carries (jobs == 0: none).
+struct XgSide {
+    const int32_t *tau;
+    int64_t ti;            // index of the iteration's first draw
+    int64_t q, rem;
+    int bmax;
+    int jobs;
+    double *out;           // [3][bmax][bmax]
+};
+
 // Vector-type tag: double (FP64 solve) or float (FP32/BF16 storage solve).
 enum VecType { VEC_F64 = 0, VEC_F32 = 1 };
 
@@ -59,7 +73,8 @@ struct Layout {
     // selection chunks (whole blocks)
     int64_t bpc;          // blocks per selection chunk
     int32_t nch_s;        // selection chunks
-    int32_t pad_;
+    int32_t nch_f;        // fused forward steps: column slabs
+    int64_t wf;           //   columns per slab (sub-slabs of 64 (FP64) or 128 columns)
 };
 
 }  // namespace rorbk
@@ -101,6 +116,11 @@ struct rorbk_handle_s {
     void *d_xold;             // x before the step's update (vector type, n)
     void *d_dxp;              // update column partials [row chunk][n] (vector type)
     double *d_P[2];           // partial A_S x per update chunk [nch][bmax]
+    int32_t fast3;            // 1: fused forward steps (k_fwd.hip)
+    double *d_P3;             // fused path: partial products of three blocks [nch][3 bmax]
+    double *d_XG;             // fused path: cross-Grams, two slots [2][3][bmax][bmax]
+    double *d_z3;             // fused path: z = b_S - A_S x of the next three blocks
+    uint32_t *d_fwdcnt;       // fused path: greedy workgroups done, 0 between launches
     double *d_axp;            // residual partial products [nseg][m]
     void *d_r;                // residual (vector type)
     double *d_bn;             // per-block ||r_t||^2
@@ -281,6 +301,27 @@ hipError_t launch_step_dense(const rorbk_handle_s *h, const StepArgs &a, hipStre
 hipError_t launch_residual_dense(const rorbk_handle_s *h, const void *A, int dt,
                                  int aligned, int vec, const void *x, double *axp,
                                  hipStream_t s);
+hipError_t launch_residual_dense_side(const rorbk_handle_s *h, const void *A, int dt,
+                                      int aligned, int vec, const void *x, double *axp,
+                                      const XgSide &side, hipStream_t s);
+// fused forward steps (dense, blocks of at most RORBK_FWD_MAX_BLOCK rows)
+struct FwdArgs {
+    const void *A;        // matrix values (dtype dt)
+    int dt;
+    int aligned;
+    int vec;
+    const void *b;        // right-hand side (vector type)
+    void *x;              // iterate (vector type)
+    const int32_t *I;     // greedy rows (NULL: products only)
+    const double *y;      // greedy solution y_I
+    int64_t tau_index;    // first draw of the iteration (samp3) or of the next one (greedy; < 0: none)
+    const double *xg;     // cross-Grams of the iteration (samp3)
+};
+hipError_t launch_fwd_greedy(const rorbk_handle_s *h, const FwdArgs &a, hipStream_t s);
+hipError_t launch_fwd_samp3(const rorbk_handle_s *h, const FwdArgs &a, hipStream_t s);
+hipError_t launch_xgram(const rorbk_handle_s *h, const void *A, int dt, int aligned, int64_t ti,
+                        double *out, hipStream_t s);
+int fwd_xgram_jobs(int bmax);
 hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt,
                              const int32_t *idx, int K, double *Gpart, hipStream_t s);
 hipError_t launch_step_csr(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
