@@ -1,8 +1,9 @@
 // k_fwd.hip -- the forward iteration's block steps for dense row-major
 // matrices whose blocks have at most FWD_B rows (row form): the three sampled
 // updates of an outer iteration (Algorithm 1, inner loop) in one launch, the
-// greedy update fused with the next iteration's products, and the cross-Grams
-// of the three sampled blocks.
+// greedy update fused with the next iteration's products, the cross-Grams
+// of the three sampled blocks, and the chain form in which the greedy update
+// of iteration it and the sampled updates of iteration it + 1 share one pass.
 //
 // The three sampled steps x1 = x0 + A1^T y1, x2 = x1 + A2^T y2,
 // x3 = x2 + A3^T y3 with y_l = H_l (b_l - A_l x_{l-1}) (Lemma 2's update
@@ -55,14 +56,105 @@ __device__ __forceinline__ void split3(const Blk3 &B, int qq, int *l, int *i, in
 template <typename T>
 __host__ __device__ constexpr int fwd_swc() { return sizeof(T) == 8 ? 64 : 128; }
 
-template <typename T, bool AL>
-__global__ __launch_bounds__(256) void k_xgram(const T *__restrict__ A, int64_t ld, int64_t n,
-                                               const int32_t *__restrict__ tau, int64_t ti,
-                                               int64_t q, int64_t rem, int bmax,
-                                               double *__restrict__ out,
-                                               const Ctrl *__restrict__ ctrl) {
+template <typename T, bool AL, int NW>
+__global__ __launch_bounds__(64 * NW) void k_xgram(const T *__restrict__ A, int64_t ld, int64_t n,
+                                                   const int32_t *__restrict__ tau, int64_t ti,
+                                                   int64_t q, int64_t rem, int bmax,
+                                                   double *__restrict__ out,
+                                                   const Ctrl *__restrict__ ctrl) {
     if (ctrl->done) return;
-    xgram_tile<T, AL>(A, ld, n, tau, ti, q, rem, bmax, blockIdx.x, out);
+    xgram_tile<T, AL, NW>(A, ld, n, tau, ti, q, rem, bmax, blockIdx.x, out);
+}
+
+// ------------------------------------------------- Grams of the chain form --
+// After the selection of iteration it, with the blocks S' drawn for iteration
+// it + 1 at tau[ti .. ti+2]: the greedy Gram A_I A_I^T (packed lower) and
+// C = A_{S'} A_I^T (C[(l * FWD_B + i) * 64 + j] = <row i of block l, row I_j>),
+// as partial sums over nch column chunks (chunk ch at G + ch * K(K+1)/2 and
+// C + ch * CHAIN_C).  Since A_{S'} (x + A_I^T y) = A_{S'} x + C y, the next
+// iteration's z = b_{S'} - A_{S'} x_new = r_{S'} - C y follows from the
+// residual r of this iteration (taken at x, before the greedy step) once y is
+// known, with no pass over x in between.  One 16 x 16 tile of one chunk per
+// workgroup: the GC_W waves take consecutive column ranges (multiples of the
+// MFMA step) and are summed in wave order.  (The cross-Grams of S' do not
+// depend on I and are formed by spare workgroups of the selection.)
+constexpr int GC_W = 8;
+constexpr int CHAIN_C = 3 * FWD_B * 64;   // doubles of one chunk of C
+
+struct GramChainP {
+    const void *A;
+    int64_t ld, n, q, rem;
+    int bmax;
+    const int32_t *I;
+    int K;
+    const int32_t *tau;
+    int64_t ti;
+    int64_t wc;     // columns per chunk (a multiple of 32)
+    double *G;      // [nch][K (K + 1) / 2], packed lower
+    double *C;      // [nch][3 * FWD_B][64]
+    const Ctrl *ctrl;
+};
+
+__host__ __device__ inline int gram_chain_tiles(int K, int bmax) {
+    const int nt = (K + 15) / 16, nb = (bmax + 15) / 16;
+    return nt * (nt + 1) / 2 + 3 * nb * nt;
+}
+
+template <typename T, bool AL>
+__global__ __launch_bounds__(64 * GC_W) void k_gram_chain(GramChainP p) {
+    if (p.ctrl->done) return;
+    constexpr int E = (sizeof(T) == 8) ? 4 : Tr<T>::VW;
+    const T *__restrict__ A = (const T *)p.A;
+    const int K = p.K;
+    const int nt = (K + 15) / 16, ntg = nt * (nt + 1) / 2;
+    const int nb = (p.bmax + 15) / 16, nc = 3 * nb * nt;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+    const int job = (int)blockIdx.x % (ntg + nc), ch = (int)blockIdx.x / (ntg + nc);
+    int kind, bi, bj, l = 0, ca = K;
+    int64_t ra, rb;
+    if (job < ntg) {                 // greedy Gram, lower tiles
+        kind = 0;
+        tile_of(job, nt, &bi, &bj);
+        ra = (bi * 16 + li < K) ? (int64_t)p.I[bi * 16 + li] : -1;
+        rb = (bj * 16 + li < K) ? (int64_t)p.I[bj * 16 + li] : -1;
+    } else if (job < ntg + nc) {     // C: block l of S' against I
+        kind = 1;
+        const int c = job - ntg;
+        l = c / (nb * nt);
+        const int rest = c - l * nb * nt;
+        bi = rest / nt;
+        bj = rest - bi * nt;
+        const int64_t t = p.tau[p.ti + l];
+        ca = blk_rows(t, p.q, p.rem);
+        if (bi * 16 >= ca) return;   // uniform: a tile past the block
+        ra = (bi * 16 + li < ca) ? blk_start(t, p.q, p.rem) + bi * 16 + li : -1;
+        rb = (bj * 16 + li < K) ? (int64_t)p.I[bj * 16 + li] : -1;
+    }
+    const int64_t c0 = (int64_t)ch * p.wc;
+    const int64_t c1 = (c0 + p.wc < p.n) ? c0 + p.wc : p.n;
+    const int64_t stepc = 4 * E;
+    const int64_t span = ((c1 - c0 + GC_W * stepc - 1) / (GC_W * stepc)) * stepc;
+    const int64_t wa = c0 + (int64_t)w * span;
+    const int64_t wb = (wa + span < c1) ? wa + span : c1;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (wa < wb) mfma_gram_tile<T, AL>(A, p.ld, ra, rb, wa, wb, acc);
+    __shared__ double red[GC_W][64][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double s = red[0][lane][r];
+#pragma unroll
+        for (int v = 1; v < GC_W; ++v) s += red[v][lane][r];
+        const int ii = bi * 16 + (lane >> 4) + 4 * r, jj = bj * 16 + li;
+        if (kind == 0) {
+            if (ii < K && jj <= ii) p.G[(int64_t)ch * (K * (K + 1) / 2) + pk(ii, jj)] = s;
+        } else {
+            if (ii < ca && jj < K) p.C[(int64_t)ch * CHAIN_C + (l * FWD_B + ii) * 64 + jj] = s;
+        }
+    }
 }
 
 // ------------------------------------------ greedy update + next products --
@@ -304,6 +396,9 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_greedy(FwdGreedyP p) {
 // stages are done; every thread also loads its entries of x and z, and its
 // rows of the update once the registers of the first half are free.  Each
 // stage of the chain is then register or LDS work, a shuffle and a barrier.
+// Chain form (K > 0): the previous iteration's greedy rows I with their y
+// join the update, x += A_I^T y_I + sum_l A_l^T y_l, in the same pass (z then
+// already accounts for the greedy step, see k_gram_chain).
 struct FwdSamp3P {
     const void *A;
     int64_t ld, n, q, rem;
@@ -316,6 +411,9 @@ struct FwdSamp3P {
     void *x;
     int64_t wu;
     const Ctrl *ctrl;
+    const int32_t *I;      // chain form: the greedy rows of the previous iteration
+    int K;                 // (0: none) and their y, applied in the same pass
+    const double *y;
 };
 
 constexpr int MC = (FWD_B + 1) / 2;          // matrix entries per thread and row pair
@@ -399,8 +497,11 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
 
     __shared__ V s_x[1024];
     __shared__ V s_red[G][SWC];
-    __shared__ double s_z[3 * FWD_B], s_y[3 * FWD_B];
+    __shared__ double s_z[3 * FWD_B], s_y[3 * FWD_B + 64];
     __shared__ double s_m[3 * FWD_B * LDM];
+    static_assert(64 + 3 * FWD_B <= FWD_T, "one row-table entry per thread");
+    __shared__ int32_t s_row[64 + 3 * FWD_B], s_slot[64 + 3 * FWD_B];
+    const int K = p.K;
 
     // --- every load of the kernel, in the order the data is needed
     V xv[(1024 + FWD_T - 1) / FWD_T];
@@ -411,6 +512,13 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
         xv[u] = (c < wcols) ? t : (V)0;
     }
     const double zv = p.z3[tid < 3 * FWD_B ? tid : 0];
+    // chain form: the greedy rows and their y (uniform branch)
+    int32_t iv = 0;
+    double ygv = 0.0;
+    if (K > 0) {
+        iv = p.I[tid < K ? tid : 0];
+        ygv = p.y[tid < K ? tid : 0];
+    }
     // the first three matrices of the chain, one per thread range
     const int rg = tid / (2 * FWD_B), uu = tid - rg * 2 * FWD_B, ir = uu >> 1, h = uu & 1;
     double m[MC];
@@ -439,15 +547,16 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
         fv[u] = ok ? t : 0.0;
     }
     // row r of this thread's share of the update: its index in A (row 0
-    // stands in past the three blocks) and its slot in y (recomputed where
-    // needed rather than held in registers)
+    // stands in past the last row) and its slot in s_y, read from the LDS
+    // tables each time it is needed (volatile: not held in registers across
+    // the chain).  The greedy rows come first.
+    const int nrows = K + ncnt;
     auto urow = [&](int r, int64_t *row, int *slot) -> bool {
         const int qq = g + G * r;
-        int l, i;
-        split3(B, qq < ncnt ? qq : 0, &l, &i, row);
-        *slot = l * FWD_B + i;
-        if (qq >= ncnt) *row = 0;
-        return qq < ncnt;
+        const bool ok = qq < nrows;
+        *row = ok ? (int64_t)((volatile int32_t *)s_row)[qq] : 0;
+        *slot = ok ? ((volatile int32_t *)s_slot)[qq] : 0;
+        return ok;
     };
 
     // --- z = b_S - A_S x0 (slots l * FWD_B + i; s_y zeroed)
@@ -459,6 +568,15 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
     if (tid < 3 * FWD_B) {
         s_z[tid] = zv;
         s_y[tid] = 0.0;
+    }
+    if (tid < K) s_y[3 * FWD_B + tid] = ygv;
+    // the row tables of the update: entry tid (fewer than FWD_T rows)
+    if (tid < nrows) {
+        int l, i;
+        int64_t r3;
+        split3(B, tid >= K ? tid - K : 0, &l, &i, &r3);
+        s_row[tid] = (tid < K) ? iv : (int32_t)r3;
+        s_slot[tid] = (tid < K) ? 3 * FWD_B + tid : l * FWD_B + i;
     }
     __syncthreads();
     // y1 = H1 z1
@@ -606,17 +724,20 @@ static hipError_t greedy_launch_cls(const FwdGreedyP &p, int nblk, int cls, hipS
     return hipGetLastError();
 }
 
-// rows of the three blocks per thread: 4, 8 or 13
+// rows of the update per thread (the three blocks and, in the chain form,
+// the greedy rows): 4, 8, 13 or 17
 template <typename T, typename V, bool AL, bool MS>
 static hipError_t samp3_launch_rn(const FwdSamp3P &p, int nblk, int bmax, hipStream_t s) {
     constexpr int G = fwd_groups<T>();
-    const int rn = (3 * bmax + G - 1) / G;
+    const int rn = (3 * bmax + p.K + G - 1) / G;
     if (rn <= 4)
         hipLaunchKernelGGL((k_fwd_samp3<T, V, AL, 4, MS>), dim3(nblk), dim3(FWD_T), 0, s, p);
     else if (rn <= 8)
         hipLaunchKernelGGL((k_fwd_samp3<T, V, AL, 8, MS>), dim3(nblk), dim3(FWD_T), 0, s, p);
-    else
+    else if (rn <= 13)
         hipLaunchKernelGGL((k_fwd_samp3<T, V, AL, 13, MS>), dim3(nblk), dim3(FWD_T), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_fwd_samp3<T, V, AL, 17, MS>), dim3(nblk), dim3(FWD_T), 0, s, p);
     return hipGetLastError();
 }
 
@@ -670,6 +791,9 @@ static hipError_t fwd_samp3_typed(const rorbk_handle_s *h, const FwdArgs &a, hip
     p.x = a.x;
     p.wu = L.wf;
     p.ctrl = h->d_ctrl;
+    p.I = a.I;
+    p.K = a.I ? (int)L.K : 0;
+    p.y = a.y;
     const int bm = (int)L.bmax;
     const bool ms = L.wf > fwd_swc<T>();
     if (a.aligned) {
@@ -692,29 +816,71 @@ hipError_t launch_fwd_samp3(const rorbk_handle_s *h, const FwdArgs &a, hipStream
     return fwd_samp3_typed<bf16_t, float>(h, a, s);
 }
 
-template <typename T>
+template <typename T, int NW>
 static hipError_t xgram_typed(const rorbk_handle_s *h, const void *A, int aligned, int64_t ti,
                               double *out, hipStream_t s) {
     const Layout &L = h->L;
     const int jobs = xgram_jobs((int)L.bmax);
     if (aligned)
-        hipLaunchKernelGGL((k_xgram<T, true>), dim3(jobs), dim3(256), 0, s, (const T *)A, L.ld,
-                           L.n, h->d_tau, ti, L.q, L.rem, (int)L.bmax, out,
+        hipLaunchKernelGGL((k_xgram<T, true, NW>), dim3(jobs), dim3(64 * NW), 0, s, (const T *)A,
+                           L.ld, L.n, h->d_tau, ti, L.q, L.rem, (int)L.bmax, out,
                            (const Ctrl *)h->d_ctrl);
     else
-        hipLaunchKernelGGL((k_xgram<T, false>), dim3(jobs), dim3(256), 0, s, (const T *)A, L.ld,
-                           L.n, h->d_tau, ti, L.q, L.rem, (int)L.bmax, out,
+        hipLaunchKernelGGL((k_xgram<T, false, NW>), dim3(jobs), dim3(64 * NW), 0, s,
+                           (const T *)A, L.ld, L.n, h->d_tau, ti, L.q, L.rem, (int)L.bmax, out,
                            (const Ctrl *)h->d_ctrl);
     return hipGetLastError();
 }
 
+// waves: 4 (stand-alone starts, the residual's spare workgroups) or 8 (the
+// selection's spare workgroups; the same sums when a chained solve resumes)
 hipError_t launch_xgram(const rorbk_handle_s *h, const void *A, int dt, int aligned, int64_t ti,
-                        double *out, hipStream_t s) {
-    if (dt == RORBK_F64) return xgram_typed<double>(h, A, aligned, ti, out, s);
-    if (dt == RORBK_F32) return xgram_typed<float>(h, A, aligned, ti, out, s);
-    return xgram_typed<bf16_t>(h, A, aligned, ti, out, s);
+                        double *out, int waves, hipStream_t s) {
+    if (waves == 8) {
+        if (dt == RORBK_F64) return xgram_typed<double, 8>(h, A, aligned, ti, out, s);
+        if (dt == RORBK_F32) return xgram_typed<float, 8>(h, A, aligned, ti, out, s);
+        return xgram_typed<bf16_t, 8>(h, A, aligned, ti, out, s);
+    }
+    if (dt == RORBK_F64) return xgram_typed<double, 4>(h, A, aligned, ti, out, s);
+    if (dt == RORBK_F32) return xgram_typed<float, 4>(h, A, aligned, ti, out, s);
+    return xgram_typed<bf16_t, 4>(h, A, aligned, ti, out, s);
 }
 
 int fwd_xgram_jobs(int bmax) { return xgram_jobs(bmax); }
+
+template <typename T>
+static hipError_t gram_chain_typed(const rorbk_handle_s *h, const GramChainP &p, int aligned,
+                                   hipStream_t s) {
+    const int jobs = gram_chain_tiles(p.K, p.bmax) * h->L.nch_c;
+    if (aligned)
+        hipLaunchKernelGGL((k_gram_chain<T, true>), dim3(jobs), dim3(64 * GC_W), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_gram_chain<T, false>), dim3(jobs), dim3(64 * GC_W), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_chain(const rorbk_handle_s *h, const void *A, int dt, int aligned,
+                             const int32_t *I, int64_t ti, double *G, hipStream_t s) {
+    const Layout &L = h->L;
+    if (L.K > 64 || L.bmax > FWD_B || !h->d_C) return hipErrorInvalidValue;
+    GramChainP p;
+    p.A = A;
+    p.ld = L.ld;
+    p.n = L.n;
+    p.q = L.q;
+    p.rem = L.rem;
+    p.bmax = (int)L.bmax;
+    p.I = I;
+    p.K = (int)L.K;
+    p.tau = h->d_tau;
+    p.ti = ti;
+    p.wc = L.wc;
+    p.G = G;
+    p.C = h->d_C;
+    p.ctrl = h->d_ctrl;
+    if (dt == RORBK_F64) return gram_chain_typed<double>(h, p, aligned, s);
+    if (dt == RORBK_F32) return gram_chain_typed<float>(h, p, aligned, s);
+    return gram_chain_typed<bf16_t>(h, p, aligned, s);
+}
 
 }  // namespace rorbk

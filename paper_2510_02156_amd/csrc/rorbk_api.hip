@@ -174,6 +174,8 @@ void free_solve_buffers(rorbk_handle_s *h) {
     h->rec_cap = 0;
     dfree(h->d_ckpt);
     h->ckpt_cap = 0;
+    dfree(h->d_ckst);
+    h->ckst_cap = 0;
 }
 
 void destroy_all(rorbk_handle_s *h) {
@@ -192,6 +194,7 @@ void destroy_all(rorbk_handle_s *h) {
     dfree(h->d_XG);
     dfree(h->d_z3);
     dfree(h->d_fwdcnt);
+    dfree(h->d_C);
     dfree(h->d_axp);
     dfree(h->d_r);
     dfree(h->d_bn);
@@ -279,6 +282,11 @@ int ensure_solve_buffers(rorbk_handle_s *h, int64_t iters, bool record_I, int64_
             CHK(dalloc((char **)&h->d_ckpt, (size_t)need));
             h->ckpt_cap = need;
         }
+        if (h->chain && h->ckst_cap < ckpt_slots) {
+            dfree(h->d_ckst);
+            CHK(dalloc(&h->d_ckst, (size_t)(ckpt_slots * CKST_DOUBLES)));
+            h->ckst_cap = ckpt_slots;
+        }
     }
     return RORBK_OK;
 }
@@ -294,6 +302,8 @@ struct RunOpts {
     const int32_t *replay_I;   // device, indexed by iteration
     int64_t ckpt_every;        // 0: none
     void *ckpt;                // checkpoint slots (vector type)
+    bool resume_chain;         // chain form: the sampled steps of it0 are done
+                               // (restored from a checkpoint's chain state)
 };
 
 // Iterations [it0, it1) of Algorithm 1 on the device; stops early once the
@@ -323,12 +333,22 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     fa.b = o.b;
     fa.x = o.x;
     const int64_t xgs = 3 * L.bmax * L.bmax;   // one slot of cross-Grams
-    if (fused) {
+    // chain form: iteration it ends with the greedy update and the sampled
+    // steps of it + 1 in one pass, unless it + 1 is the end.  A checkpoint at
+    // it + 1 then keeps the state that pass starts from (x before it, the
+    // greedy rows, y and the next z), from which the recomputation resumes
+    // with the same arithmetic.
+    const bool chain = fused && h->chain != 0;
+    auto chain_next = [&](int64_t it) -> bool { return chain && it + 1 < it1; };
+    bool prev_chained = chain && o.resume_chain;
+    if (prev_chained) {
+        // the caller restored x, I, y, z and ran the sampled steps of it0
+    } else if (fused) {
         // the first iteration's three-block products and cross-Grams
         fa.I = nullptr;
         fa.tau_index = 3 * it0;
         HIPCHK(launch_fwd_greedy(h, fa, s));
-        HIPCHK(launch_xgram(h, o.A, o.dt, o.aligned, 3 * it0, h->d_XG + (it0 & 1) * xgs, s));
+        HIPCHK(launch_xgram(h, o.A, o.dt, o.aligned, 3 * it0, h->d_XG + (it0 & 1) * xgs, 4, s));
     } else {
         // partial products of the first sampled step
         a.cur.kind = -1;
@@ -359,15 +379,19 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
     int64_t chunk = 0;
     bool done = false;
     for (int64_t it = it0; it < it1; ++it) {
-        if (o.ckpt_every > 0 && (it % o.ckpt_every) == 0) {
+        if (o.ckpt_every > 0 && (it % o.ckpt_every) == 0 && !prev_chained) {
             char *dst = (char *)o.ckpt + (size_t)(it / o.ckpt_every) * L.n * vec_size(o.vec);
             HIPCHK(hipMemcpyAsync(dst, o.x, (size_t)L.n * vec_size(o.vec),
                                   hipMemcpyDeviceToDevice, s));
         }
         if (fused) {
-            fa.tau_index = 3 * it;
-            fa.xg = h->d_XG + (it & 1) * xgs;
-            HIPCHK(launch_fwd_samp3(h, fa, s));
+            if (!prev_chained) {
+                fa.I = nullptr;
+                fa.y = nullptr;
+                fa.tau_index = 3 * it;
+                fa.xg = h->d_XG + (it & 1) * xgs;
+                HIPCHK(launch_fwd_samp3(h, fa, s));
+            }
         } else {
             for (int l = 0; l < 3; ++l) {
                 a.cur.kind = 0;
@@ -390,9 +414,10 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
         if (timed) HIPCHK(hipEventRecord(h->evr[chunk & 1][0], s));
         if (fused) {
             // the next iteration's cross-Grams ride along in spare workgroups
+            // (the chain form forms them after the selection)
             XgSide side = {h->d_tau, 3 * (it + 1), L.q, L.rem, (int)L.bmax, 0,
                            h->d_XG + ((it + 1) & 1) * xgs};
-            if (it + 1 < it1) side.jobs = fwd_xgram_jobs((int)L.bmax);
+            if (it + 1 < it1 && !chain) side.jobs = fwd_xgram_jobs((int)L.bmax);
             HIPCHK(launch_residual_dense_side(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_axp, side,
                                               s));
         } else {
@@ -420,20 +445,51 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
         sa.rI_out = h->d_rI;
         sa.stop_test = 1;
         sa.skip_topk = 0;
+        if (chain_next(it)) {
+            // the next iteration's cross-Grams in the selection's spare workgroups
+            sa.xg_out = h->d_XG + ((it + 1) & 1) * xgs;
+            sa.xg_A = o.A;
+            sa.xg_dt = o.dt;
+            sa.xg_aligned = o.aligned;
+            sa.xg_ti = 3 * (it + 1);
+        }
         HIPCHK(launch_select(h, sa, s));
-        if (h->col) {
+        if (chain_next(it)) {
+            // greedy Gram and C; y and the next z; the greedy update with the
+            // next iteration's sampled steps
+            double *xgn = h->d_XG + ((it + 1) & 1) * xgs;
+            HIPCHK(launch_gram_chain(h, o.A, o.dt, o.aligned, h->d_I, 3 * (it + 1), h->d_G, s));
+            double *ckst = nullptr;
+            if (o.ckpt_every > 0 && ((it + 1) % o.ckpt_every) == 0) {
+                const int64_t slot = (it + 1) / o.ckpt_every;
+                char *dst = (char *)o.ckpt + (size_t)slot * L.n * vec_size(o.vec);
+                HIPCHK(hipMemcpyAsync(dst, o.x, (size_t)L.n * vec_size(o.vec),
+                                      hipMemcpyDeviceToDevice, s));
+                ckst = h->d_ckst + slot * CKST_DOUBLES;
+            }
+            HIPCHK(launch_chol_chain(h, h->d_G, h->d_r, o.vec, 3 * (it + 1), ckst, s));
+            fa.I = h->d_I;
+            fa.y = h->d_y;
+            fa.tau_index = 3 * (it + 1);
+            fa.xg = xgn;
+            HIPCHK(launch_fwd_samp3(h, fa, s));
+            prev_chained = true;
+        } else if (h->col) {
             HIPCHK(launch_col_greedy(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_I, (int)L.K,
                                      h->d_rI, h->d_y, s));
         } else {
             HIPCHK(gram(h, o.A, o.dt, o.aligned, h->d_I, (int)L.K, h->d_G));
             HIPCHK(launch_chol_solve(h, h->d_G, (int)L.K, h->d_rI, nullptr, h->d_y, s));
         }
-        if (fused) {
+        if (chain_next(it)) {
+            // done above
+        } else if (fused) {
             // greedy update and the next iteration's three-block products
             fa.I = h->d_I;
             fa.y = h->d_y;
             fa.tau_index = (it + 1 < it1) ? 3 * (it + 1) : -1;
             HIPCHK(launch_fwd_greedy(h, fa, s));
+            prev_chained = false;
         } else {
             a.cur.kind = 1;
             a.cur.count = (int32_t)L.K;
@@ -671,6 +727,19 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         ALLOC(h->d_XG, 2 * 3 * bmax * bmax);
         ALLOC(h->d_z3, 3 * RORBK_FWD_MAX_BLOCK);
         ALLOC(h->d_fwdcnt, 1);
+        // chain form: greedy sets of at most 64 rows, rows of at most 4096
+        // columns (Grams after the selection in up to 4 column chunks of at
+        // least 512) and a selection that merges its candidates in one level
+        h->chain = (L.K <= 64 && L.n <= 4096 && L.nch_s * L.K <= 8192) ? 1 : 0;
+        if (h->chain) {
+            int64_t nc = (L.n + 511) / 512;
+            if (nc > 4) nc = 4;
+            int64_t wc = (L.n + nc - 1) / nc;
+            wc = ((wc + 31) / 32) * 32;
+            L.wc = wc;
+            L.nch_c = (int32_t)((L.n + wc - 1) / wc);
+            ALLOC(h->d_C, (int64_t)L.nch_c * 3 * RORBK_FWD_MAX_BLOCK * 64);
+        }
     }
     ALLOC(h->d_axp, (int64_t)L.nseg * L.m);
     {
@@ -1501,6 +1570,40 @@ int ror_bk_backward(rorbk_handle h, const void *grad_x, void *grad_b, void *grad
             rc = launch_set_thr(h->d_ctrl, h->rec_thr, s) == hipSuccess ? RORBK_OK
                      : fail(RORBK_ERR_HIP, "threshold restore failed");
             if (rc) break;
+            if (h->chain && sg > 0) {
+                // the checkpoint holds the chain state of iteration a: restore
+                // the greedy rows, y and z, form the cross-Grams of a's blocks
+                // as the forward did, and take a's sampled steps together
+                // with the greedy update of a - 1, as the forward did
+                const double *st = h->d_ckst + sg * CKST_DOUBLES;
+                he = hipMemcpyAsync(h->d_I, st, L.K * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+                if (he == hipSuccess)
+                    he = hipMemcpyAsync(h->d_y, st + 32, L.K * sizeof(double),
+                                        hipMemcpyDeviceToDevice, s);
+                if (he == hipSuccess)
+                    he = hipMemcpyAsync(h->d_z3, st + 96, 3 * RORBK_FWD_MAX_BLOCK * sizeof(double),
+                                        hipMemcpyDeviceToDevice, s);
+                double *xga = h->d_XG + (a & 1) * 3 * L.bmax * L.bmax;
+                if (he == hipSuccess)
+                    he = launch_xgram(h, h->A, L.dtype, h->aligned, 3 * a, xga, 8, s);
+                if (he == hipSuccess) {
+                    FwdArgs fa;
+                    memset(&fa, 0, sizeof(fa));
+                    fa.A = h->A;
+                    fa.dt = L.dtype;
+                    fa.aligned = h->aligned;
+                    fa.vec = vec;
+                    fa.b = h->rec_b;
+                    fa.x = xw;
+                    fa.I = h->d_I;
+                    fa.y = h->d_y;
+                    fa.tau_index = 3 * a;
+                    fa.xg = xga;
+                    he = launch_fwd_samp3(h, fa, s);
+                }
+                if (he != hipSuccess) { rc = fail(RORBK_ERR_HIP, "chain state restore failed"); break; }
+                o.resume_chain = true;
+            }
             int64_t ran = 0;
             bool stopped = false;
             rc = run_iterations(h, o, a, e, &ran, &stopped);

@@ -490,7 +490,7 @@ __device__ __forceinline__ void ldl_steps(std::integer_sequence<int, Ks...>, dou
 // solution unchanged and keeps the N unrolled steps free of branches; lanes
 // from N on carry no row and their values are never used.
 template <int N>
-__device__ inline bool ldl_wave(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
+__device__ __forceinline__ bool ldl_wave(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
                                 double *Lc /* 64*65 */) {
     const int lane = threadIdx.x & 63;
     double a[N];
@@ -515,7 +515,7 @@ __device__ inline bool ldl_wave(const double *Gp, double *z, int K, double *colb
 }
 
 // K <= 64 on one wave: the 32-row form when it suffices.
-__device__ inline bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf,
+__device__ __forceinline__ bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf,
                                   double *Lc) {
     return (K <= 32) ? ldl_wave<32>(Gp, z, K, colbuf, Lc) : ldl_wave<64>(Gp, z, K, colbuf, Lc);
 }

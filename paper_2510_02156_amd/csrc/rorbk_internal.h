@@ -75,6 +75,8 @@ struct Layout {
     int32_t nch_s;        // selection chunks
     int32_t nch_f;        // fused forward steps: column slabs
     int64_t wf;           //   columns per slab (sub-slabs of 64 (FP64) or 128 columns)
+    int32_t nch_c;        // chain form: column chunks of the Grams after the selection
+    int64_t wc;           //   columns per chunk (a multiple of 32)
 };
 
 }  // namespace rorbk
@@ -120,6 +122,8 @@ struct rorbk_handle_s {
     double *d_P3;             // fused path: partial products of three blocks [nch][3 bmax]
     double *d_XG;             // fused path: cross-Grams, two slots [2][3][bmax][bmax]
     double *d_z3;             // fused path: z = b_S - A_S x of the next three blocks
+    int32_t chain;            // chain form of the fused path (K <= 64, n <= 4096)
+    double *d_C;              // chain form: A_{S'} A_I^T, [3 * FWD_B][64]
     uint32_t *d_fwdcnt;       // fused path: greedy workgroups done, 0 between launches
     double *d_axp;            // residual partial products [nseg][m]
     void *d_r;                // residual (vector type)
@@ -153,6 +157,9 @@ struct rorbk_handle_s {
     int64_t ckpt_every;
     void *d_ckpt;             // x checkpoints (vector type) [(cap/c)+1][n]
     int64_t ckpt_cap;
+    double *d_ckst;           // chain form: the rest of each checkpoint's state
+                              // [slots][CKST_DOUBLES] (greedy rows, y, next z)
+    int64_t ckst_cap;
     const void *rec_b;        // b of the recorded solve (CHECKPOINT recompute)
     uint64_t rec_seed;
     int32_t rec_vec;          // vector type of the recorded solve
@@ -242,6 +249,13 @@ struct SelectArgs {
     double *rI_out;
     int stop_test;        // 1: compare with thr2 and set done
     int skip_topk;        // 1: only norms (refinement outer residual)
+    // spare workgroups (may be unset): the cross-Grams of the blocks drawn at
+    // tau[xg_ti .. xg_ti+2] into xg_out, computed alongside the selection
+    double *xg_out;
+    const void *xg_A;
+    int xg_dt;
+    int xg_aligned;
+    int64_t xg_ti;
 };
 hipError_t launch_select(const rorbk_handle_s *h, const SelectArgs &a, hipStream_t s);
 
@@ -312,7 +326,8 @@ struct FwdArgs {
     int vec;
     const void *b;        // right-hand side (vector type)
     void *x;              // iterate (vector type)
-    const int32_t *I;     // greedy rows (NULL: products only)
+    const int32_t *I;     // greedy rows (greedy: NULL for products only; samp3: the
+                          // chain form's greedy rows, NULL for none)
     const double *y;      // greedy solution y_I
     int64_t tau_index;    // first draw of the iteration (samp3) or of the next one (greedy; < 0: none)
     const double *xg;     // cross-Grams of the iteration (samp3)
@@ -320,8 +335,17 @@ struct FwdArgs {
 hipError_t launch_fwd_greedy(const rorbk_handle_s *h, const FwdArgs &a, hipStream_t s);
 hipError_t launch_fwd_samp3(const rorbk_handle_s *h, const FwdArgs &a, hipStream_t s);
 hipError_t launch_xgram(const rorbk_handle_s *h, const void *A, int dt, int aligned, int64_t ti,
-                        double *out, hipStream_t s);
+                        double *out, int waves, hipStream_t s);
 int fwd_xgram_jobs(int bmax);
+// chain form: Grams after the selection (greedy Gram, C, next cross-Grams) and
+// the greedy solve that also forms the next iteration's z
+hipError_t launch_gram_chain(const rorbk_handle_s *h, const void *A, int dt, int aligned,
+                             const int32_t *I, int64_t ti, double *G, hipStream_t s);
+// ckst (may be NULL): a checkpoint's chain state, I (raw int32) in doubles
+// [0, 32), y in [32, 96), the next z in [96, 96 + 3 * RORBK_FWD_MAX_BLOCK)
+constexpr int CKST_DOUBLES = 320;
+hipError_t launch_chol_chain(const rorbk_handle_s *h, const double *G, const void *r, int vec,
+                             int64_t ti, double *ckst, hipStream_t s);
 hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt,
                              const int32_t *idx, int K, double *Gpart, hipStream_t s);
 hipError_t launch_step_csr(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
