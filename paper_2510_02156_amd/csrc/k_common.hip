@@ -792,146 +792,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int q = threadIdx.x; q < K; q += 64) y[q] = z[q];
 }
 
-// Chain form (dense rows, K <= 64, blocks of at most FWD_B = RORBK_FWD_MAX_BLOCK
-// rows): the greedy solve of iteration it as in k_chol_wave, then the start of
-// iteration it + 1's three sampled steps,
-// z[l * FWD_B + i] = r[row i of block l] - sum_j C[(l * FWD_B + i) * 64 + j] y_j
-// (j ascending; zero in unused slots), with r the residual of this iteration
-// and C = A_{S'} A_I^T.  G and C arrive as nch <= CH_NCH column-chunk partials,
-// summed in chunk order; waves 1-3 sum C into LDS while wave 0 factors.
-constexpr int CH_B = RORBK_FWD_MAX_BLOCK;
-constexpr int CH_LDC = 65;   // LDS row stride of C (odd: no bank conflicts per slot)
-constexpr int CH_NCH = 4;    // most column chunks of the chain form's Grams
-
-template <typename V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_chain(
-    const double *__restrict__ G, int nch, int K, double lambda, const double *__restrict__ rI,
-    const double *__restrict__ C, const V *__restrict__ r, const int32_t *__restrict__ tau,
-    int64_t ti, int64_t q, int64_t rem, double *__restrict__ y, double *__restrict__ z3,
-    const int32_t *__restrict__ I, double *__restrict__ ckst, Ctrl *__restrict__ ctrl) {
-    constexpr int NTH = 256, NU = (64 * 65 / 2 + NTH - 1) / NTH;
-    __shared__ double Gp[64 * 65 / 2];
-    __shared__ double z[64];
-    __shared__ double colbuf[2 * MAXB];
-    __shared__ double Lc[64 * 65];
-    __shared__ double Cs[3 * CH_B * CH_LDC];
-    __shared__ double rs[3 * CH_B];
-    __shared__ int32_t rs_ok[3 * CH_B];
-    __shared__ int s_ok;
-    const int tid = threadIdx.x, w = tid >> 6;
-    const int stop = __hip_atomic_load(&ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int KP = K * (K + 1) / 2;
-    // every chunk's entries in flight together (clamped addresses, unused
-    // chunks scaled by zero), then summed in chunk order
-    double gt[CH_NCH][NU];
-#pragma unroll
-    for (int c = 0; c < CH_NCH; ++c)
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int f = tid + u * NTH;
-            gt[c][u] = G[(int64_t)(c < nch ? c : 0) * KP + (f < KP ? f : 0)];
-        }
-    double gv[NU];
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        gv[u] = gt[0][u];
-#pragma unroll
-        for (int c = 1; c < CH_NCH; ++c) gv[u] += (c < nch) ? gt[c][u] : 0.0;
-    }
-    // the residual at the next blocks' rows (threads of the slots)
-    double rv = 0.0;
-    bool slot_ok = false;
-    if (tid < 3 * CH_B) {
-        const int l = tid / CH_B, i = tid - l * CH_B;
-        const int64_t t = tau[ti + l];
-        slot_ok = i < blk_rows(t, q, rem);
-        const V rr = r[blk_start(t, q, rem) + (slot_ok ? i : 0)];
-        rv = slot_ok ? (double)rr : 0.0;
-    }
-    const double ri = rI[tid < K ? tid : 0];
-    if (stop) return;
-#pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int f = tid + u * NTH;
-        if (f < KP) Gp[f] = gv[u];
-    }
-    if (tid < K) z[tid] = ri;
-    if (tid < 3 * CH_B) {
-        rs[tid] = rv;
-        rs_ok[tid] = slot_ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (tid < K) Gp[pk(tid, tid)] += lambda;
-    __syncthreads();
-    if (w == 0) {
-        const bool ok = ldl_wave64(Gp, z, K, colbuf, Lc);
-        if (tid == 0) {
-            s_ok = ok ? 1 : 0;
-            if (!ok) {
-                ctrl->status = RORBK_ERR_NOT_SPD;
-                ctrl->done = 1;
-            }
-        }
-    } else {
-        // C into LDS: 192 threads, 65 entries each, in batches of 13 entries x
-        // every chunk in flight (every address in bounds; entries of unused
-        // rows or columns read as zero)
-        constexpr int NCE = 3 * CH_B * 64, PT = NCE / 192, UB = 13;
-        static_assert(PT * 192 == NCE && PT % UB == 0, "C splits evenly");
-        const int t = tid - 64;
-        for (int ub = 0; ub < PT; ub += UB) {
-            double ct[CH_NCH][UB];
-#pragma unroll
-            for (int c = 0; c < CH_NCH; ++c)
-#pragma unroll
-                for (int u = 0; u < UB; ++u)
-                    ct[c][u] = C[(int64_t)(c < nch ? c : 0) * NCE + t + (ub + u) * 192];
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                double v = ct[0][u];
-#pragma unroll
-                for (int c = 1; c < CH_NCH; ++c) v += (c < nch) ? ct[c][u] : 0.0;
-                const int e = t + (ub + u) * 192;
-                const int sl = e >> 6, j = e & 63;
-                Cs[sl * CH_LDC + j] = (j < K) ? v : 0.0;
-            }
-        }
-    }
-    __syncthreads();
-    if (!s_ok) return;
-    if (tid < K) y[tid] = z[tid];
-    if (tid < 3 * CH_B) {
-        double acc = 0.0;
-        const double *c = Cs + tid * CH_LDC;
-        for (int j = 0; j < K; ++j) acc = __builtin_fma(c[j], z[j], acc);
-        const double zz = rs_ok[tid] ? rs[tid] - acc : 0.0;
-        z3[tid] = zz;
-        if (ckst) ckst[96 + tid] = zz;
-    }
-    // a checkpoint: the greedy rows and y as well (the next steps' inputs)
-    if (ckst && tid < K) {
-        reinterpret_cast<int32_t *>(ckst)[tid] = I[tid];
-        ckst[32 + tid] = z[tid];
-    }
-}
-
-hipError_t launch_chol_chain(const rorbk_handle_s *h, const double *G, const void *r, int vec,
-                             int64_t ti, double *ckst, hipStream_t s) {
-    const Layout &L = h->L;
-    if (L.K > 64 || L.bmax > CH_B || !h->d_C || L.nch_c < 1 || L.nch_c > CH_NCH)
-        return hipErrorInvalidValue;
-    static_assert(96 + 3 * CH_B <= CKST_DOUBLES, "a checkpoint's chain state fits its slot");
-    if (vec == VEC_F64)
-        hipLaunchKernelGGL(k_chol_chain<double>, dim3(1), dim3(256), 0, s, G, (int)L.nch_c,
-                           (int)L.K, h->lambda, h->d_rI, h->d_C, (const double *)r, h->d_tau, ti,
-                           L.q, L.rem, h->d_y, h->d_z3, h->d_I, ckst, h->d_ctrl);
-    else
-        hipLaunchKernelGGL(k_chol_chain<float>, dim3(1), dim3(256), 0, s, G, (int)L.nch_c,
-                           (int)L.K, h->lambda, h->d_rI, h->d_C, (const float *)r, h->d_tau, ti,
-                           L.q, L.rem, h->d_y, h->d_z3, h->d_I, ckst, h->d_ctrl);
-    return hipGetLastError();
-}
-
 hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K,
                              const double *rI, const double *Pin, double *y, hipStream_t s) {
     const Layout &L = h->L;

@@ -701,6 +701,316 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
     for (int c = tid; c < wcols; c += FWD_T) x[c0 + c] = s_x[c];
 }
 
+// ------------------------------------------------------- chain step kernel --
+// The rest of iteration it after the chain form's Grams (k_gram_chain), in one
+// launch over the column slabs (one sub-slab each): in every workgroup wave 0
+// solves the greedy system (G + lambda I) y = r_I (ldl_wave64 on the summed
+// Gram chunks; every workgroup forms the same y) while waves 1-7 sum C into
+// LDS and load the three sampled steps' matrices into registers, so that their
+// memory latency is spent during the factorisation.  Then
+// z = r_{S'} - C y (j ascending), the chain of k_fwd_samp3 with the same
+// arithmetic (the same thread of a row pair, the same sums), and
+// x[cols] += A_I[:, cols]^T y + sum_l A_l[:, cols]^T y_l in one pass.  The
+// first workgroup writes y and, for a checkpoint, the chain state (I, y, z).
+struct FwdChainP {
+    const void *A;
+    int64_t ld, n, q, rem;
+    int bmax;
+    const int32_t *tau;
+    int64_t tau_index;     // first draw of iteration it + 1
+    const double *H;
+    const double *xg;      // cross-Grams of iteration it + 1's blocks
+    const double *G;       // [nch][K (K + 1) / 2] packed lower partials
+    const double *C;       // [nch][3 * FWD_B][64] partials
+    int nch;
+    int K;
+    double lambda;
+    const double *rI;
+    const void *r;         // residual of iteration it (vector type)
+    const int32_t *I;
+    void *x;
+    int64_t wu;            // columns per workgroup (one sub-slab)
+    double *y;
+    double *ckst;          // NULL, or a checkpoint's chain state
+    Ctrl *ctrl;
+};
+
+constexpr int CHN = 4;                       // most column chunks of G and C
+constexpr int FC_T = FWD_T - 64;             // threads of waves 1-7
+constexpr int FILL2 = (3 * FWD_B * FWD_B + FC_T - 1) / FC_T;   // H2, G32, H3 entries per thread
+constexpr int LA = 64 * 65 / 2 + 64 * 65 + 2 * MAXB;          // LDS doubles: Gp | Lc | colbuf
+
+template <typename T, typename V, bool AL, int RN>
+__global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
+    constexpr int VW = Tr<T>::VW;
+    constexpr int SWC = fwd_swc<T>();
+    constexpr int NV = SWC / VW;
+    constexpr int G = FWD_T / NV;
+    static_assert(1024 + G * SWC * sizeof(V) / 8 <= LA, "phase-2 arrays fit the factorisation's LDS");
+    const T *__restrict__ A = (const T *)p.A;
+    V *__restrict__ x = (V *)p.x;
+    const int tid = threadIdx.x;
+    const int K = p.K, KP = K * (K + 1) / 2;
+    // LDS: region a holds the factorisation (packed Gram, L, column buffers),
+    // then z, y and the update's row sums; region b holds C, then H2, G32, H3
+    __shared__ double lds_a[LA];
+    __shared__ double lds_b[3 * FWD_B * LDM];
+    __shared__ double s_yk[64], s_rs[3 * FWD_B];
+    __shared__ int32_t s_rok[3 * FWD_B];
+    __shared__ V s_x[SWC];
+    __shared__ int32_t s_row[64 + 3 * FWD_B], s_slot[64 + 3 * FWD_B];
+    __shared__ int s_ok;
+    double *Gp = lds_a, *Lc = lds_a + 64 * 65 / 2, *colbuf = Lc + 64 * 65;
+    double *s_z = lds_a, *s_y = lds_a + 256;
+    V (*s_red)[SWC] = reinterpret_cast<V (*)[SWC]>(lds_a + 1024);
+
+    // --- phase 0: the Gram chunks (summed in chunk order) and r_I
+    constexpr int NU0 = (64 * 65 / 2 + FWD_T - 1) / FWD_T;
+    {
+        const int stop =
+            __hip_atomic_load(&p.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double gt[CHN][NU0];
+#pragma unroll
+        for (int c = 0; c < CHN; ++c)
+#pragma unroll
+            for (int u = 0; u < NU0; ++u) {
+                const int f = tid + u * FWD_T;
+                gt[c][u] = p.G[(int64_t)(c < p.nch ? c : 0) * KP + (f < KP ? f : 0)];
+            }
+        const double ri = p.rI[tid < K ? tid : 0];
+        if (stop) return;
+#pragma unroll
+        for (int u = 0; u < NU0; ++u) {
+            const int f = tid + u * FWD_T;
+            double gs = gt[0][u];
+#pragma unroll
+            for (int c = 1; c < CHN; ++c) gs += (c < p.nch) ? gt[c][u] : 0.0;
+            if (f < KP) Gp[f] = gs;
+        }
+        if (tid < K) s_yk[tid] = ri;
+    }
+    __syncthreads();
+    if (tid < K) Gp[pk(tid, tid)] += p.lambda;
+    __syncthreads();
+
+    // --- phase 1: wave 0 factors (nothing else is live across it; the
+    // wave index is made scalar so that both branches are real jumps) ...
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wv == 0) {
+        const bool ok = ldl_wave64(Gp, s_yk, K, colbuf, Lc);
+        if (tid == 0) {
+            s_ok = ok ? 1 : 0;
+            if (!ok) {
+                p.ctrl->status = RORBK_ERR_NOT_SPD;
+                p.ctrl->done = 1;
+            }
+        }
+    }
+    // ... while waves 1-7 load everything else
+    double m[MC];
+    double fv[FILL2];
+    if (wv != 0) {
+        const int t = tid - 64;
+        const int rg = t / (2 * FWD_B), uu = t - rg * 2 * FWD_B, ir = uu >> 1, h = uu & 1;
+        Blk3 B;
+        blocks3(p.tau, p.tau_index, p.q, p.rem, B);
+        const int64_t hoff0 = blk_hoff(p.tau[p.tau_index], p.q, p.rem);
+        const int64_t hoff1 = blk_hoff(p.tau[p.tau_index + 1], p.q, p.rem);
+        const int64_t hoff2 = blk_hoff(p.tau[p.tau_index + 2], p.q, p.rem);
+        const int ncnt = B.c0 + B.c1 + B.c2, nrows = K + ncnt;
+        const int bm = p.bmax, n0 = B.c0, n1 = B.c1, n2 = B.c2;
+        const int64_t c0 = (int64_t)blockIdx.x * p.wu;
+        const int wcols = (int)(((c0 + p.wu < p.n) ? c0 + p.wu : p.n) - c0);
+        // r at the next blocks' rows, the greedy rows, the slab of x
+        double rsv = 0.0;
+        int rok = 0;
+        if (t < 3 * FWD_B) {
+            const int l = t / FWD_B, i = t - l * FWD_B;
+            const int cl = (l == 0) ? n0 : ((l == 1) ? n1 : n2);
+            const int64_t st = (l == 0) ? B.s0 : ((l == 1) ? B.s1 : B.s2);
+            rok = i < cl;
+            const V rr = ((const V *)p.r)[st + (rok ? i : 0)];
+            rsv = rok ? (double)rr : 0.0;
+        }
+        const int32_t iv = p.I[t < K ? t : 0];
+        const V xv = x[c0 + (t < wcols ? t : 0)];
+        // H1, G21, G31 (thread ranges of 2 FWD_B, as k_fwd_samp3)
+        {
+            const double *M = p.H;
+            int64_t sj = 1;
+            int rows = 0, cols = 0;
+            if (rg == 0) { M = p.H + hoff0; sj = n0; rows = n0; cols = n0; }
+            else if (rg == 1) { M = p.xg; sj = bm; rows = n1; cols = n0; }
+            else if (rg == 2) { M = p.xg + (int64_t)bm * bm; sj = bm; rows = n2; cols = n0; }
+            mv_load(M, 1, sj, ir, h, rows, cols, m);
+        }
+        // H2, G32, H3 for LDS (consecutive threads, consecutive addresses)
+#pragma unroll
+        for (int u = 0; u < FILL2; ++u) {
+            const int e = t + u * FC_T;
+            const int k = e / (FWD_B * FWD_B), rr = e - k * FWD_B * FWD_B;
+            const int j = rr / FWD_B, i = rr - j * FWD_B;
+            const double *M = (k == 0) ? p.H + hoff1 : ((k == 1) ? p.xg + 2 * (int64_t)bm * bm : p.H + hoff2);
+            const int rows = (k == 0) ? n1 : n2, cols = (k == 1) ? n1 : (k == 0 ? n1 : n2);
+            const int64_t sj = (k == 1) ? bm : (k == 0 ? n1 : n2);
+            const bool ok = k < 3 && i < rows && j < cols;
+            const double tv = M[ok ? i + (int64_t)j * sj : 0];
+            fv[u] = ok ? tv : 0.0;
+        }
+        if (t < 3 * FWD_B) {
+            s_rs[t] = rsv;
+            s_rok[t] = rok;
+        }
+        if (t < wcols) s_x[t] = xv;
+        if (t < nrows) {   // the update's row tables, greedy rows first
+            int l, i;
+            int64_t r3;
+            split3(B, t >= K ? t - K : 0, &l, &i, &r3);
+            s_row[t] = (t < K) ? iv : (int32_t)r3;
+            s_slot[t] = (t < K) ? 3 * FWD_B + t : l * FWD_B + i;
+        }
+        // C summed over its chunks into LDS (row stride LDM), in batches
+        constexpr int NCE = 3 * FWD_B * 64, PT = (NCE + FC_T - 1) / FC_T, UB = 7;
+        for (int ub = 0; ub < PT; ub += UB) {
+            double ct[CHN][UB];
+#pragma unroll
+            for (int c = 0; c < CHN; ++c)
+#pragma unroll
+                for (int u = 0; u < UB; ++u) {
+                    const int e = t + (ub + u) * FC_T;
+                    ct[c][u] = p.C[(int64_t)(c < p.nch ? c : 0) * NCE + (e < NCE ? e : 0)];
+                }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int e = t + (ub + u) * FC_T;
+                double cs = ct[0][u];
+#pragma unroll
+                for (int c = 1; c < CHN; ++c) cs += (c < p.nch) ? ct[c][u] : 0.0;
+                const int sl = e >> 6, j = e & 63;
+                if (e < NCE) lds_b[sl * LDM + j] = (j < K) ? cs : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+
+    // --- phase 2: z = r_{S'} - C y, then the chain (the sizes again, from
+    // the draws)
+    Blk3 B;
+    blocks3(p.tau, p.tau_index, p.q, p.rem, B);
+    const int ncnt = B.c0 + B.c1 + B.c2, nrows = K + ncnt;
+    const int n0 = B.c0, n1 = B.c1, n2 = B.c2;
+    const int64_t c0 = (int64_t)blockIdx.x * p.wu;
+    const int64_t c1 = (c0 + p.wu < p.n) ? c0 + p.wu : p.n;
+    const int wcols = (int)(c1 - c0);
+    const int t = tid - 64;
+    const int rg = t / (2 * FWD_B), uu = t - rg * 2 * FWD_B, ir = uu >> 1, h = uu & 1;
+    const int g = tid / NV, v = tid % NV;
+    if (tid < 3 * FWD_B) {
+        double acc = 0.0;
+        const double *cr = lds_b + tid * LDM;
+        for (int j = 0; j < K; ++j) acc = __builtin_fma(cr[j], s_yk[j], acc);
+        const double zz = s_rok[tid] ? s_rs[tid] - acc : 0.0;
+        s_z[tid] = zz;
+        s_y[tid] = 0.0;
+        if (blockIdx.x == 0 && p.ckst) p.ckst[96 + tid] = zz;
+    }
+    if (tid < K) {
+        s_y[3 * FWD_B + tid] = s_yk[tid];
+        if (blockIdx.x == 0) {
+            p.y[tid] = s_yk[tid];
+            if (p.ckst) {
+                reinterpret_cast<int32_t *>(p.ckst)[tid] = s_row[tid];
+                p.ckst[32 + tid] = s_yk[tid];
+            }
+        }
+    }
+    __syncthreads();
+    // H2, G32, H3 into LDS (C is no longer needed); y1 = H1 z1
+    if (wv != 0) {
+#pragma unroll
+        for (int u = 0; u < FILL2; ++u) {
+            const int e = t + u * FC_T;
+            if (e < 3 * FWD_B * FWD_B) {
+                const int k = e / (FWD_B * FWD_B), rr = e - k * FWD_B * FWD_B;
+                const int j = rr / FWD_B, i = rr - j * FWD_B;
+                lds_b[k * FWD_B * LDM + i * LDM + j] = fv[u];
+            }
+        }
+        if (rg == 0) {
+            const double d = mv_dot(m, s_z, h);
+            if (h == 0 && ir < n0) s_y[ir] = d;
+        }
+    }
+    __syncthreads();
+    // z2 -= G21 y1 and z3 -= G31 y1
+    if (wv != 0 && (rg == 1 || rg == 2)) {
+        const double d = mv_dot(m, s_y, h);
+        const int rows = (rg == 1) ? n1 : n2;
+        if (h == 0 && ir < rows) s_z[rg * FWD_B + ir] -= d;
+    }
+    // the update's rows load during the rest of the chain
+    auto urow = [&](int r, int64_t *row, int *slot) -> bool {
+        const int qq = g + G * r;
+        const bool ok = qq < nrows;
+        *row = ok ? (int64_t)((volatile int32_t *)s_row)[qq] : 0;
+        *slot = ok ? ((volatile int32_t *)s_slot)[qq] : 0;
+        return ok;
+    };
+    const int64_t col = c0 + (int64_t)v * VW;
+    uvec4 ua[RN];
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+        int64_t row;
+        int slot;
+        const bool ok = urow(r, &row, &slot);
+        ua[r] = load_raw_sel<T, AL>(A + row * p.ld, col, c1, ok, A, c0);
+    }
+    __syncthreads();
+    // y2 = H2 z2
+    if (wv != 0 && rg == 0) {
+        const double d = mv_dot_lds(lds_b, ir, s_z + FWD_B, h);
+        if (h == 0 && ir < n1) s_y[FWD_B + ir] = d;
+    }
+    __syncthreads();
+    // z3 -= G32 y2
+    if (wv != 0 && rg == 1) {
+        const double d = mv_dot_lds(lds_b + FWD_B * LDM, ir, s_y + FWD_B, h);
+        if (h == 0 && ir < n2) s_z[2 * FWD_B + ir] -= d;
+    }
+    __syncthreads();
+    // y3 = H3 z3
+    if (wv != 0 && rg == 2) {
+        const double d = mv_dot_lds(lds_b + 2 * FWD_B * LDM, ir, s_z + 2 * FWD_B, h);
+        if (h == 0 && ir < n2) s_y[2 * FWD_B + ir] = d;
+    }
+    __syncthreads();
+
+    // --- x[cols] += A_I^T y + sum_l A_l^T y_l (one sub-slab)
+    V acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = (V)0;
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+        int64_t row;
+        int slot;
+        const bool ok = urow(r, &row, &slot);
+        const V yr = ok ? (V)s_y[slot] : (V)0;
+        V av[VW];
+        cvt_raw<T, V>(ua[r], av);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = fmaT(av[e], yr, acc[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < VW; ++e) s_red[g][v * VW + e] = acc[e];
+    __syncthreads();
+    if (tid < wcols) {
+        V sx = (V)0;
+        for (int gg = 0; gg < G; ++gg) sx += s_red[gg][tid];
+        x[c0 + tid] = s_x[tid] + sx;
+    }
+}
+
 // ------------------------------------------------------------ launchers --
 // Size class of the per-thread row counts: rows of one block (RC) and of
 // three (RN) per thread for G row groups.
@@ -847,6 +1157,62 @@ hipError_t launch_xgram(const rorbk_handle_s *h, const void *A, int dt, int alig
 }
 
 int fwd_xgram_jobs(int bmax) { return xgram_jobs(bmax); }
+
+template <typename T, typename V, bool AL>
+static hipError_t fwd_chain_rn(const FwdChainP &p, int nblk, hipStream_t s) {
+    constexpr int G = fwd_groups<T>();
+    const int rn = (3 * p.bmax + p.K + G - 1) / G;
+    if (rn <= 4)
+        hipLaunchKernelGGL((k_fwd_chain<T, V, AL, 4>), dim3(nblk), dim3(FWD_T), 0, s, p);
+    else if (rn <= 8)
+        hipLaunchKernelGGL((k_fwd_chain<T, V, AL, 8>), dim3(nblk), dim3(FWD_T), 0, s, p);
+    else if (rn <= 13)
+        hipLaunchKernelGGL((k_fwd_chain<T, V, AL, 13>), dim3(nblk), dim3(FWD_T), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_fwd_chain<T, V, AL, 17>), dim3(nblk), dim3(FWD_T), 0, s, p);
+    return hipGetLastError();
+}
+
+template <typename T, typename V>
+static hipError_t fwd_chain_typed(const rorbk_handle_s *h, const FwdArgs &a, const void *r,
+                                  double *ckst, hipStream_t s) {
+    const Layout &L = h->L;
+    if (L.wf != fwd_swc<T>() || L.K > 64 || L.bmax > FWD_B || L.nch_c < 1 || L.nch_c > CHN)
+        return hipErrorInvalidValue;   // one sub-slab per workgroup, the chain form's sizes
+    FwdChainP p;
+    p.A = a.A;
+    p.ld = L.ld;
+    p.n = L.n;
+    p.q = L.q;
+    p.rem = L.rem;
+    p.bmax = (int)L.bmax;
+    p.tau = h->d_tau;
+    p.tau_index = a.tau_index;
+    p.H = h->d_H;
+    p.xg = a.xg;
+    p.G = h->d_G;
+    p.C = h->d_C;
+    p.nch = L.nch_c;
+    p.K = (int)L.K;
+    p.lambda = h->lambda;
+    p.rI = h->d_rI;
+    p.r = r;
+    p.I = a.I;
+    p.x = a.x;
+    p.wu = L.wf;
+    p.y = h->d_y;
+    p.ckst = ckst;
+    p.ctrl = h->d_ctrl;
+    if (a.aligned) return fwd_chain_rn<T, V, true>(p, L.nch_f, s);
+    return fwd_chain_rn<T, V, false>(p, L.nch_f, s);
+}
+
+hipError_t launch_fwd_chain(const rorbk_handle_s *h, const FwdArgs &a, const void *r,
+                            double *ckst, hipStream_t s) {
+    if (a.vec == VEC_F64) return fwd_chain_typed<double, double>(h, a, r, ckst, s);
+    if (a.dt == RORBK_F32) return fwd_chain_typed<float, float>(h, a, r, ckst, s);
+    return fwd_chain_typed<bf16_t, float>(h, a, r, ckst, s);
+}
 
 template <typename T>
 static hipError_t gram_chain_typed(const rorbk_handle_s *h, const GramChainP &p, int aligned,

@@ -467,12 +467,11 @@ int run_iterations(rorbk_handle_s *h, const RunOpts &o, int64_t it0, int64_t it1
                                       hipMemcpyDeviceToDevice, s));
                 ckst = h->d_ckst + slot * CKST_DOUBLES;
             }
-            HIPCHK(launch_chol_chain(h, h->d_G, h->d_r, o.vec, 3 * (it + 1), ckst, s));
             fa.I = h->d_I;
             fa.y = h->d_y;
             fa.tau_index = 3 * (it + 1);
             fa.xg = xgn;
-            HIPCHK(launch_fwd_samp3(h, fa, s));
+            HIPCHK(launch_fwd_chain(h, fa, h->d_r, ckst, s));
             prev_chained = true;
         } else if (h->col) {
             HIPCHK(launch_col_greedy(h, o.A, o.dt, o.aligned, o.vec, o.x, h->d_I, (int)L.K,

@@ -495,8 +495,12 @@ __device__ __forceinline__ bool ldl_wave(const double *Gp, double *z, int K, dou
     const int lane = threadIdx.x & 63;
     double a[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-        a[j] = (lane < K && j < K) ? ((j <= lane) ? Gp[pk(lane, j)] : 0.0) : (j == lane ? 1.0 : 0.0);
+    for (int j = 0; j < N; ++j) {
+        // every lane reads an entry of its own packed row (no read behind a
+        // branch), the upper part is then replaced by zeros
+        const double gv = Gp[pk(lane, j <= lane ? j : lane)];
+        a[j] = (lane < K && j < K) ? ((j <= lane) ? gv : 0.0) : (j == lane ? 1.0 : 0.0);
+    }
     double zi = (lane < K) ? z[lane] : 0.0;
     colbuf[lane] = a[0];
     __builtin_amdgcn_wave_barrier();

@@ -337,15 +337,18 @@ hipError_t launch_fwd_samp3(const rorbk_handle_s *h, const FwdArgs &a, hipStream
 hipError_t launch_xgram(const rorbk_handle_s *h, const void *A, int dt, int aligned, int64_t ti,
                         double *out, int waves, hipStream_t s);
 int fwd_xgram_jobs(int bmax);
-// chain form: Grams after the selection (greedy Gram, C, next cross-Grams) and
-// the greedy solve that also forms the next iteration's z
+// chain form: the Grams after the selection (greedy Gram and C = A_S' A_I^T in
+// column chunks)
 hipError_t launch_gram_chain(const rorbk_handle_s *h, const void *A, int dt, int aligned,
                              const int32_t *I, int64_t ti, double *G, hipStream_t s);
 // ckst (may be NULL): a checkpoint's chain state, I (raw int32) in doubles
 // [0, 32), y in [32, 96), the next z in [96, 96 + 3 * RORBK_FWD_MAX_BLOCK)
 constexpr int CKST_DOUBLES = 320;
-hipError_t launch_chol_chain(const rorbk_handle_s *h, const double *G, const void *r, int vec,
-                             int64_t ti, double *ckst, hipStream_t s);
+static_assert(96 + 3 * RORBK_FWD_MAX_BLOCK <= CKST_DOUBLES, "a checkpoint's chain state fits");
+// the greedy solve, the next z, the next sampled steps and the combined update
+// in one launch (a.I: greedy rows, a.tau_index / a.xg: iteration it + 1)
+hipError_t launch_fwd_chain(const rorbk_handle_s *h, const FwdArgs &a, const void *r,
+                            double *ckst, hipStream_t s);
 hipError_t launch_gram_dense(const rorbk_handle_s *h, const void *A, int dt,
                              const int32_t *idx, int K, double *Gpart, hipStream_t s);
 hipError_t launch_step_csr(const rorbk_handle_s *h, const StepArgs &a, hipStream_t s);
