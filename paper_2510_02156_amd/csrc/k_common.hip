@@ -79,16 +79,25 @@ hipError_t launch_copy_tau(const int32_t *src, int32_t *dst, int64_t count, hipS
 }
 
 // ----------------------------------------------------------------- norms --
-// ||v||^2 in a fixed order: one workgroup, contiguous thread ranges, then
-// the workgroup sum.
+// ||v||^2 in a fixed order: one workgroup, thread t summing entries t,
+// t + 1024, ... in order (each load instruction reads consecutive entries,
+// eight in flight per thread), then the workgroup sum.
 template <typename V>
 __global__ __launch_bounds__(1024) void k_norm2(const V *__restrict__ v, int64_t len,
                                                 double *__restrict__ out) {
     __shared__ double sh[16];
-    const int64_t per = (len + blockDim.x - 1) / blockDim.x;
-    const int64_t a = threadIdx.x * per, e = (a + per < len) ? a + per : len;
+    constexpr int U = 8;
+    const int64_t st = blockDim.x;
     double s = 0.0;
-    for (int64_t i = a; i < e; ++i) {
+    int64_t i = threadIdx.x;
+    for (; i + (U - 1) * st < len; i += U * st) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = (double)v[i + u * st];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s = __builtin_fma(t[u], t[u], s);
+    }
+    for (; i < len; i += st) {
         const double t = (double)v[i];
         s = __builtin_fma(t, t, s);
     }
@@ -808,29 +817,49 @@ hipError_t launch_chol_solve(const rorbk_handle_s *h, const double *Gpart, int K
 
 // ------------------------------------------------------ initial solution --
 // Algorithm 2 (appendix): y = the sum of the rows of A, kept from the setup as
-// the sum of the block row-sums (centroids) in block order.
-__global__ __launch_bounds__(256) void k_colsum(const double *__restrict__ cen, int64_t k,
-                                                int64_t n, double *__restrict__ y) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// the sum of the block row-sums (centroids).  A workgroup takes 64 columns;
+// wave w sums the blocks of its contiguous sixteenth in block order (one
+// coalesced 64-column read per block, eight in flight), and wave 0 adds the
+// sixteen partial sums in wave order.
+__global__ __launch_bounds__(1024) void k_colsum(const double *__restrict__ cen, int64_t k,
+                                                 int64_t n, double *__restrict__ y) {
+    __shared__ double part[16][64];
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t per = (k + 15) / 16;
+    const int64_t t0 = w * per, t1 = (t0 + per < k) ? t0 + per : k;
+    const int64_t jc = (j < n) ? j : n - 1;
     double s = 0.0;
-    for (int64_t t = 0; t < k; ++t) s += cen[t * n + j];
-    y[j] = s;
+    int64_t t = t0;
+    for (; t + U <= t1; t += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = cen[(t + u) * n + jc];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; t < t1; ++t) s += cen[t * n + jc];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < n) {
+        double a = part[0][lane];
+        for (int v2 = 1; v2 < 16; ++v2) a += part[v2][lane];
+        y[j] = a;
+    }
 }
 
 // The coefficient <b, b~> / ||b~||^2 of Algorithm 2 with b~ = A y given as the
-// residual pass's segment products (summed in segment order): per-thread sums
-// over a contiguous run of rows, then a fixed-order workgroup sum.
+// residual pass's segment products (summed in segment order): thread t sums
+// rows t, t + 1024, ... in order, then a fixed-order workgroup sum.
 // out[0] = <b, b~>, out[1] = ||b~||^2, out[2] = the coefficient (0 if b~ = 0).
 template <typename V>
 __global__ __launch_bounds__(1024) void k_alg2_coef(const V *__restrict__ b,
                                                     const double *__restrict__ axp, int nseg,
                                                     int64_t m, double *__restrict__ out) {
     __shared__ double sh[16];
-    const int64_t per = (m + blockDim.x - 1) / blockDim.x;
-    const int64_t a = threadIdx.x * per, e = (a + per < m) ? a + per : m;
     double sb = 0.0, st = 0.0;
-    for (int64_t i = a; i < e; ++i) {
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {   // coalesced, rows in order per thread
         double bt = 0.0;
         for (int sg = 0; sg < nseg; ++sg) bt += axp[(int64_t)sg * m + i];
         sb = __builtin_fma((double)b[i], bt, sb);
@@ -854,7 +883,7 @@ __global__ __launch_bounds__(256) void k_scale_vec(const double *__restrict__ y,
 }
 
 hipError_t launch_colsum(const double *cen, int64_t k, int64_t n, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cen, k, n, y);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, cen, k, n, y);
     return hipGetLastError();
 }
 

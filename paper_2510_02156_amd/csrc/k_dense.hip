@@ -491,23 +491,42 @@ __global__ __launch_bounds__(256) void k_cos_mfma(const double *__restrict__ cen
 
 // S_t = sum of the tile partials in tile order, Pbar_t = exp(-2 S_t / n)
 // (Section 2, the proposal), and W = running sums of Pbar in block order.
-__global__ __launch_bounds__(256) void k_proposal(const double *__restrict__ Sp, int64_t ntile,
-                                                  int64_t k, int64_t n, double *__restrict__ S,
-                                                  double *__restrict__ pbar,
-                                                  double *__restrict__ W) {
-    for (int64_t t = threadIdx.x; t < k; t += blockDim.x) {
-        double s = 0.0;
-        for (int64_t j = 0; j < ntile; ++j) s += Sp[t * ntile + j];
+// S_t (the |cos| row sums, from the per-tile partials) and pbar_t: one wave
+// per block, lane l summing tiles l, l + 64, ... in order, then a fixed
+// butterfly.
+__global__ __launch_bounds__(256) void k_proposal_rows(const double *__restrict__ Sp,
+                                                       int64_t ntile, int64_t k, int64_t n,
+                                                       double *__restrict__ S,
+                                                       double *__restrict__ pbar) {
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= k) return;   // uniform per wave
+    double s = 0.0;
+    for (int64_t j = lane; j < ntile; j += 64) s += Sp[t * ntile + j];
+    s = group_sum(s, 64);
+    if (lane == 0) {
         S[t] = s;
         pbar[t] = exp(-2.0 * s / (double)n);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc = 0.0;
-        for (int64_t t = 0; t < k; ++t) {
-            acc += pbar[t];
-            W[t] = acc;
+}
+
+// W = the running sum of pbar, in block order (one thread; pbar staged in LDS
+// by the workgroup first).
+__global__ __launch_bounds__(1024) void k_proposal(const double *__restrict__ pbar, int64_t k,
+                                                   double *__restrict__ W) {
+    __shared__ double sp[8192];
+    for (int64_t c0 = 0; c0 < k; c0 += 8192) {
+        const int64_t c1 = (c0 + 8192 < k) ? c0 + 8192 : k;
+        for (int64_t t = c0 + threadIdx.x; t < c1; t += blockDim.x) sp[t - c0] = pbar[t];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double acc = (c0 > 0) ? W[c0 - 1] : 0.0;
+            for (int64_t t = c0; t < c1; ++t) {
+                acc += sp[t - c0];
+                W[t] = acc;
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -524,8 +543,9 @@ hipError_t launch_proposal_from_centroids(const rorbk_handle_s *h, double *cen, 
     else
         hipLaunchKernelGGL(k_cos_mfma<false>, dim3((unsigned)tiles), dim3(256), 0, s, cen, L.k,
                            L.n, nrm, Sp, ntc);
-    hipLaunchKernelGGL(k_proposal, dim3(1), dim3(256), 0, s, Sp, ntc, L.k, L.n, h->d_S,
-                       h->d_pbar, h->d_W);
+    hipLaunchKernelGGL(k_proposal_rows, dim3((unsigned)((L.k + 3) / 4)), dim3(256), 0, s, Sp, ntc,
+                       L.k, L.n, h->d_S, h->d_pbar);
+    hipLaunchKernelGGL(k_proposal, dim3(1), dim3(1024), 0, s, h->d_pbar, L.k, h->d_W);
     return hipGetLastError();
 }
 
@@ -666,43 +686,69 @@ __global__ __launch_bounds__(256) void k_block_inverse(const double *__restrict_
     }
 }
 
-// Same for blocks of at most 64 rows on one wave: LDL^T in registers
-// (ldl_wave64), then column j of the inverse by lane j from the factor.
-__global__ __launch_bounds__(64) void k_block_inverse64(const double *__restrict__ Gs,
-                                                        int64_t kpmax, int64_t q, int64_t rem,
-                                                        double lambda, double *__restrict__ H,
-                                                        int32_t *__restrict__ fail) {
-    __shared__ double Gp[64 * 65 / 2];
-    __shared__ double z[64];
-    __shared__ double colbuf[128];
-    __shared__ double Lc[64 * 65];
+// Blocks of at most KM rows: the same LDL^T (ldl_solve on 4 x 4 tiles), then the inverse in
+// LDS: M = L^{-1} column by column (four threads per column j:
+// m_ij = [i == j] - sum_{p<i} l_ip m_pj, thread q of the four summing the
+// p = q mod 4 terms in order, the four partials added by a fixed butterfly;
+// all columns run the same i, so l_ip is a broadcast read), and
+// H = M^T D^{-1} M entry by entry (h_ij = sum_{p >= max(i,j)} (m_pi m_pj) / d_p,
+// the product taken in an order-free way so that H is exactly symmetric),
+// written row-major with consecutive threads on consecutive entries.
+template <int KM>
+__global__ __launch_bounds__(4 * KM) void k_block_inverse_lds(const double *__restrict__ Gs,
+                                                           int64_t kpmax, int64_t q, int64_t rem,
+                                                           double lambda, double *__restrict__ H,
+                                                           int32_t *__restrict__ fail) {
+    __shared__ double Gp[KM * (KM + 1) / 2];
+    __shared__ double z[KM];
+    __shared__ double colbuf[2 * MAXB];
+    __shared__ double invd[KM];
+    __shared__ double M[KM][KM + 1];
     const int64_t t = blockIdx.x;
     const int K = blk_rows(t, q, rem);
     const int KP = K * (K + 1) / 2;
-    const int lane = threadIdx.x;
-    for (int f = lane; f < KP; f += 64) Gp[f] = Gs[t * kpmax + f];
-    z[lane] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    if (lane < K) Gp[pk(lane, lane)] += lambda;
-    __builtin_amdgcn_wave_barrier();
-    if (!ldl_wave64(Gp, z, K, colbuf, Lc)) {
-        if (lane == 0) *fail = 1;
+    for (int f = threadIdx.x; f < KP; f += blockDim.x) Gp[f] = Gs[t * kpmax + f];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) z[i] = 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < K; i += blockDim.x) Gp[pk(i, i)] += lambda;
+    __syncthreads();
+    static_assert(((KM + 3) / 4) * ((KM + 3) / 4 + 1) / 2 <= 256, "4 x 4 tiles cover the block");
+    if (!ldl_solve<4>(Gp, z, K, colbuf)) {
+        if (threadIdx.x == 0) *fail = 1;
         return;
     }
-    if (lane >= K) return;
-    const int j = lane;
-    double *h = H + blk_hoff(t, q, rem) + (int64_t)j * K;
-    for (int i = 0; i < j; ++i) h[i] = 0.0;
-    for (int i = j; i < K; ++i) {            // unit lower: z_i = e_j - sum l_ip z_p
-        double sacc = (i == j) ? 1.0 : 0.0;
-        for (int p2 = j; p2 < i; ++p2) sacc -= Lc[p2 * 65 + i] * h[p2];
-        h[i] = sacc;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) invd[i] = 1.0 / Gp[pk(i, i)];
+    __syncthreads();
+    // unit lower factor: l_ip = g_ip / d_p (i > p)
+    for (int f = threadIdx.x; f < KP; f += blockDim.x) {
+        int i = 0;
+        while (pk(i + 1, 0) <= f) ++i;
+        const int p2 = f - pk(i, 0);
+        if (p2 < i) Gp[f] *= invd[p2];
     }
-    for (int i = j; i < K; ++i) h[i] /= Lc[i * 65 + i];
-    for (int i = K - 1; i >= 0; --i) {       // L^T h = D^{-1} z
-        double sacc = h[i];
-        for (int p2 = i + 1; p2 < K; ++p2) sacc -= Lc[i * 65 + p2] * h[p2];
-        h[i] = sacc;
+    __syncthreads();
+    // M = L^{-1}, four threads per column (consecutive lanes of one wave)
+    {
+        const int j = threadIdx.x >> 2, qq = threadIdx.x & 3;
+        const int jc = (j < K) ? j : 0;
+        for (int i = 0; i < K; ++i) {
+            double part = 0.0;
+            for (int p2 = qq; p2 < i; p2 += 4) part = __builtin_fma(Gp[pk(i, p2)], M[p2][jc], part);
+            part += __shfl_xor(part, 1, 4);
+            part += __shfl_xor(part, 2, 4);
+            const double mij = (i > j) ? -part : ((i == j) ? 1.0 : 0.0);
+            if (j < K && qq == (i & 3)) M[i][j] = mij;
+        }
+    }
+    __syncthreads();
+    // H = M^T D^{-1} M
+    double *Hb = H + blk_hoff(t, q, rem);
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+        const int i = e / K, j = e - i * K;
+        const int p0 = i > j ? i : j;
+        double sacc = 0.0;
+        for (int p2 = p0; p2 < K; ++p2) sacc = __builtin_fma(M[p2][i] * M[p2][j], invd[p2], sacc);
+        Hb[e] = sacc;
     }
 }
 
@@ -746,8 +792,11 @@ hipError_t launch_block_inverses_from_grams(const rorbk_handle_s *h, const doubl
     const Layout &L = h->L;
     if (L.bmax > MAXB) return launch_big_block_inverses(h, Gs, kp, d_fail, s);
     if (L.bmax <= 64)
-        hipLaunchKernelGGL(k_block_inverse64, dim3((unsigned)L.k), dim3(64), 0, s, Gs, kp, L.q,
-                           L.rem, h->lambda, h->d_H, d_fail);
+        hipLaunchKernelGGL(k_block_inverse_lds<64>, dim3((unsigned)L.k), dim3(256), 0, s, Gs, kp,
+                           L.q, L.rem, h->lambda, h->d_H, d_fail);
+    else if (L.bmax <= 72)
+        hipLaunchKernelGGL(k_block_inverse_lds<72>, dim3((unsigned)L.k), dim3(288), 0, s, Gs, kp,
+                           L.q, L.rem, h->lambda, h->d_H, d_fail);
     else
         hipLaunchKernelGGL(k_block_inverse<8>, dim3((unsigned)L.k), dim3(256), 0, s, Gs, kp, L.q,
                            L.rem, h->lambda, h->d_H, d_fail);
