@@ -386,7 +386,19 @@ def main():
         res["error_vs_oracle"] = {
             "iters": N,
             "fp64_rel": float(np.linalg.norm(xg64.cpu().numpy() - ref["x"]) / nr),
-            f"mixed_{args.mixed}_rel": float(np.linalg.norm(xgm.cpu().numpy() - ref["x"]) / nr)}
+            f"mixed_{args.mixed}_rel": float(np.linalg.norm(xgm.cpu().numpy() - ref["x"]) / nr),
+            "note": "free-running solves: a greedy set chosen differently on a near tie "
+                    "(FP32 residuals) starts another valid trajectory; the replayed figure "
+                    "holds the selections fixed"}
+        if not csr:
+            # the low-precision passes on the oracle's own selections (replayed, no
+            # refinement): the arithmetic error alone, FP64 oracle on the FP64 matrix
+            srep = P.Solver(Amix, br, lam)
+            srep.set_replay(ref["tau"], ref["I"], N)
+            xr, _ = srep.solve(b.float(), seed=0, tol=0.0, max_iters=N, replay=True)
+            res["error_vs_oracle"][f"{args.mixed}_storage_replayed_rel"] = float(
+                np.linalg.norm(xr.double().cpu().numpy() - ref["x"]) / nr)
+            srep.close()
         log(f"error vs oracle after {N} iters: {res['error_vs_oracle']}")
 
     out = {
@@ -501,7 +513,7 @@ def cpu_baseline(O, oracle_A, br, lam, bh, seed, tol, n, need, ttt, args):
     pers = []
     ref = None
     for _ in range(3):
-        ref = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N, W=Wo, record=False)
+        ref = O.solve(oracle_A, br, lam, bh, seed=seed, tol=tol, max_iters=N, W=Wo, record=True)
         pers.append(ref["t_iter_s"] / max(ref["iters"], 1))
     per = float(np.median(pers))
     # one thread: a shorter run (about a quarter of the sample's CPU time)

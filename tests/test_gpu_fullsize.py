@@ -1,5 +1,5 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times: the tall dense 100000 x 2000 system (FP64 and FP32 storage),
+benchmark times: the tall dense 100000 x 2000 system (FP64, FP32 and BF16 storage),
 the wide 2000 x 50000 system, the 2000 x 200 system over the whole
 5000-iteration cap, and the paper's 100-block protocol on its randn 60000 x
 10000 and 1 + U(0,1) 100000 x 20000 shapes and on the column form.  Outputs
@@ -63,6 +63,20 @@ def test_tall_full_size():
     e32 = rel(host(x32), ref32["x"])
     print(f"tall full size FP32: {iters} iterations rel err {e32:.2e}", flush=True)
     assert e32 < 1e-4
+    # BF16 storage (the mixed solve's other storage), the same replay against
+    # the oracle on the BF16-rounded values: FP32 accumulation over rows of 2000
+    # BF16 products stays within the FP32 bound
+    from tests.gpu_util import bf16_tensor, bf16_values
+    del s32
+    Ab = bf16_values(A)
+    bb = Ab @ w["xstar"]
+    refb = O.solve(Ab, br, lam, bb, seed=seed, max_iters=iters)
+    sb = P.Solver(bf16_tensor(A), br, lam)
+    sb.set_replay(refb["tau"], refb["I"], iters)
+    xb, _ = sb.solve(dev(bb, torch.float32), seed=0, tol=0.0, max_iters=iters, replay=True)
+    eb = rel(host(xb), refb["x"])
+    print(f"tall full size BF16: {iters} iterations rel err {eb:.2e}", flush=True)
+    assert eb < 1e-4
 
 
 @pytest.mark.timeout(300)
