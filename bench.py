@@ -82,7 +82,7 @@ def measured_traffic(workload: str, mixed: str):
     if not hs or not tb:
         return None
     h = hashlib.sha256()
-    for f in ("k_resid.hip", "rorbk_device.h"):
+    for f in ("k_resid.hip", "rorbk_device.h", "xgram.h"):
         with open(os.path.join(ROOT, "paper_2510_02156_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return int(tb.group(1)) if h.hexdigest() == hs.group(1) else None
