@@ -23,7 +23,7 @@ def test_more_than_one_gpu_is_refused():
 def _tree(tmp_path, profile_text):
     csrc = tmp_path / "paper_2510_02156_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("k_resid.hip", "rorbk_device.h"):
+    for f in ("k_resid.hip", "rorbk_device.h", "xgram.h"):
         shutil.copy(os.path.join(ROOT, "paper_2510_02156_amd", "csrc", f), csrc / f)
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "k_resid_dense_f32_tall_100000x2000.md").write_text(profile_text)
@@ -32,7 +32,7 @@ def _tree(tmp_path, profile_text):
 
 def _sha():
     h = hashlib.sha256()
-    for f in ("k_resid.hip", "rorbk_device.h"):
+    for f in ("k_resid.hip", "rorbk_device.h", "xgram.h"):
         with open(os.path.join(ROOT, "paper_2510_02156_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
