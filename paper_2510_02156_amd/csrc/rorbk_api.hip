@@ -706,8 +706,11 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
     ALLOC(h->d_P[1], (int64_t)L.nch_u * bmax);
     // dense row-form blocks of at most RORBK_FWD_MAX_BLOCK rows: fused forward
     // steps (three-block partial products, two slots of cross-Grams)
+    // (only where the chain form applies: with many columns the fused steps'
+    // cross-Gram tiles over whole rows cost more than the separate steps)
     h->fast3 = (L.format == RORBK_DENSE && !h->big && !h->col &&
-                bmax <= RORBK_FWD_MAX_BLOCK) ? 1 : 0;
+                bmax <= RORBK_FWD_MAX_BLOCK && L.K <= 64 && L.n <= 4096 &&
+                L.nch_s * L.K <= 8192) ? 1 : 0;
     if (h->fast3) {
         // column slabs of the fused steps: sub-slabs of 64 (FP64 storage) or
         // 128 columns; one per workgroup up to 64 of them, else several, for
@@ -1027,8 +1030,9 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
     double *V = nullptr, *Z = nullptr, *small = nullptr;
     int rc = dalloc(&V, (size_t)(m * M1));
     if (!rc) rc = dalloc(&Z, (size_t)(n * max_outer));
-    // hcol (M1), R (M1 * max_outer), cs, sn (max_outer), g (M1), est (2), beta (1)
-    const size_t nsmall = (size_t)(M1 + M1 * max_outer + 2 * max_outer + M1 + 3);
+    // hcol (M1), R (M1 * max_outer), cs, sn (max_outer), g (M1), est (2), beta (1),
+    // the Gram-Schmidt partial sums (256)
+    const size_t nsmall = (size_t)(M1 + M1 * max_outer + 2 * max_outer + M1 + 3 + 256);
     if (!rc) rc = dalloc(&small, nsmall);
     if (!rc) rc = ensure_solve_buffers(h, inner_iters, false, 0, VEC_F64);
     auto cleanup = [&]() {
@@ -1041,7 +1045,7 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
         return rc;
     }
     double *hcol = small, *R = hcol + M1, *cs = R + M1 * max_outer, *sn = cs + max_outer;
-    double *g = sn + max_outer, *est = g + M1, *beta_d = est + 2;
+    double *g = sn + max_outer, *est = g + M1, *beta_d = est + 2, *gs_part = beta_d + 1;
 #define GCHK(expr)                                                                   \
     do {                                                                             \
         hipError_t e_ = (expr);                                                      \
@@ -1089,7 +1093,7 @@ int ror_bk_fabgmres(rorbk_handle h, const double *b, double *x, uint64_t seed, d
             GCHK(hipMemsetAsync(h->d_ctrl, 0, sizeof(Ctrl), s));
             GCHK(residual(h, h->A, RORBK_F64, h->aligned, VEC_F64, zk, h->d_axp));
             GCHK(launch_gmres_step(V, m, (int)k, h->d_axp, L.nseg, hcol, (int)M1, R, cs, sn, g,
-                                   est, s));
+                                   est, gs_part, s));
             double he[2];
             GCHK(hipMemcpyAsync(he, est, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
             GCHK(hipStreamSynchronize(s));

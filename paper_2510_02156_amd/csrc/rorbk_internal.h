@@ -281,7 +281,7 @@ hipError_t launch_gmres_start(const double *b, const double *axp, int nseg, int6
                               double *v1, double *g, double *out, hipStream_t s);
 hipError_t launch_gmres_step(double *V, int64_t m, int k, const double *axp, int nseg,
                              double *hcol, int M1, double *R, double *cs, double *sn, double *g,
-                             double *est, hipStream_t s);
+                             double *est, double *part /* 256 doubles */, hipStream_t s);
 hipError_t launch_gmres_update(const double *Z, int64_t n, const double *R, const double *g,
                                int kend, int M1, double *x, hipStream_t s);
 // initial solution (Algorithm 2): y = column sums of the k x n centroids
