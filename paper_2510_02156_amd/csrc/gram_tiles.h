@@ -120,4 +120,32 @@ __device__ __forceinline__ void gram64_store(const dvec4 (&acc)[4][4], int bi, i
     }
 }
 
+// The four waves' accumulators summed in wave order, as in gram64_store, and
+// the whole 64 x 64 tile written row-major, out[i * 64 + j] (on a diagonal
+// tile, `same` in gram64_accumulate, the sub-tiles above the diagonal hold
+// zeros).  Contains barriers: the whole workgroup calls it.
+__device__ __forceinline__ void gram64_store_tile(const dvec4 (&acc)[4][4],
+                                                  double *__restrict__ out) {
+    __shared__ double red[4][16][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+        if (s2 > 0) __syncthreads();
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[w][t2 * 4 + r][lane] = acc[s2][t2][r];
+        __syncthreads();
+        const int t2 = w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int q2 = t2 * 4 + r;
+            const double v = ((red[0][q2][lane] + red[1][q2][lane]) + red[2][q2][lane]) +
+                             red[3][q2][lane];
+            const int ii = s2 * 16 + (lane >> 4) + 4 * r;
+            out[ii * 64 + t2 * 16 + li] = v;
+        }
+    }
+}
+
 }  // namespace rorbk

@@ -1,6 +1,7 @@
 // k_common.hip -- format-independent ROR-BK kernels: partition, sampler,
 // norms, residual-driven selection (per-block norms, stop test, top-K) and the
 // greedy block's Cholesky solve.
+#include "ldl_blk.h"
 #include "rorbk_device.h"
 #include "xgram.h"
 
@@ -750,7 +751,7 @@ __device__ __forceinline__ void gram_sum_chunks(const double *__restrict__ Gpart
     }
 }
 
-// K <= 64: the whole solve on one wave (LDL^T in registers, ldl_wave64).
+// K <= 64: the whole solve on one wave (panel LDL^T with MFMA updates, ldl_blk64).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_chol_wave(
     const double *__restrict__ Gpart, int nch, int K, double lambda,
     const double *__restrict__ rI, const double *__restrict__ Pin, int nchP, int bmax,
@@ -758,7 +759,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     constexpr int NTH = 256;
     __shared__ double Gp[64 * 65 / 2];
     __shared__ double z[64];
-    __shared__ double colbuf[2 * MAXB];
+    __shared__ double colbuf[2 * 64];
     __shared__ double Lc[64 * 65];
     // the stop flag is read by a vector load issued with the chunk loads (the
     // Gram buffer is valid either way), so the two latencies overlap
@@ -787,11 +788,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < K; q += NTH) Gp[pk(q, q)] += lambda;
+    // the padded system (lambda on the diagonal, the identity beyond K)
+    for (int f = threadIdx.x; f < 64 * 65 / 2; f += NTH) lb_put(Lc, f, (f < KP) ? Gp[f] : 0.0, K, lambda);
+    for (int q = K + (int)threadIdx.x; q < 64; q += NTH) z[q] = 0.0;
     __syncthreads();
     // one wave from here on; the other waves leave and no block barrier follows
     if (threadIdx.x >= 64) return;
-    if (!ldl_wave64(Gp, z, K, colbuf, Lc)) {
+    if (!ldl_blk64(Lc, z, K, colbuf)) {
         if (threadIdx.x == 0) {
             ctrl->status = RORBK_ERR_NOT_SPD;
             ctrl->done = 1;

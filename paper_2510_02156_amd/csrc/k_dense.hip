@@ -433,59 +433,93 @@ __global__ __launch_bounds__(256) void k_rownorm(const double *__restrict__ cen,
 }
 
 // Cosine row sums (Section 2, C(i,j) = |<c_i,c_j>| / (|c_i||c_j|)) from the
-// centroid Gram on FP64 MFMA: one 16 x 16 tile of the lower triangle per
-// workgroup (four waves split the columns).  Tile (bi, bj) yields, for each row
-// i of block-row bi, the sum of its 16 normalised |entries| -> Sp[i][bj], and
-// (bi != bj) for each row j of block-row bj the transposed sum -> Sp[j][bi];
-// every Sp entry is written exactly once.  A zero centroid has C(t,t) = 1 and
-// C(t,j) = 0.
+// centroid Gram on FP64 MFMA, in two kernels.  k_cos64_part: grid x = lower
+// 64 x 64 tiles of the Gram, grid y = column parts of pw columns; each
+// workgroup forms its tile over its part (gram64_accumulate: four waves, each
+// loaded value feeding four products) and stores the whole tile,
+// Dp[(tile * parts + part) * 4096 + i * 64 + j].
 template <bool AL>
-__global__ __launch_bounds__(256) void k_cos_mfma(const double *__restrict__ cen, int64_t k,
-                                                  int64_t n, const double *__restrict__ nrm,
-                                                  double *__restrict__ Sp, int64_t ntc) {
+__global__ __launch_bounds__(256) void k_cos64_part(const double *__restrict__ cen, int64_t k,
+                                                    int64_t n, int64_t pw, int ntc,
+                                                    double *__restrict__ Dp) {
     int bi, bj;
-    tile_of(blockIdx.x, (int)ntc, &bi, &bj);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15;
-    const int64_t stepc = 16;   // 4 lane groups x 4 columns (FP64)
-    const int64_t span = ((n + 4 * stepc - 1) / (4 * stepc)) * stepc;
-    const int64_t wa = w * span;
-    const int64_t wb = (wa + span < n) ? wa + span : n;
-    const int64_t ra = (bi * 16 + li < k) ? bi * 16 + li : -1;
-    const int64_t rb = (bj * 16 + li < k) ? bj * 16 + li : -1;
-    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
-    if (wa < wb) mfma_gram_tile<double, AL>(cen, n, ra, rb, wa, wb, acc);
-    __shared__ double red[4][64][4];
+    tile_of(blockIdx.x, ntc, &bi, &bj);
+    if (bi < 0) return;   // uniform, before any barrier
+    const int64_t c0 = (int64_t)blockIdx.y * pw;
+    const int64_t c1 = (c0 + pw < n) ? c0 + pw : n;
+    const int li = threadIdx.x & 15;
+    const double *pa[4], *pb[4];
+    bool va[4], vb[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[w][lane][r] = acc[r];
-    __syncthreads();
-    if (w != 0) return;
-    const int64_t jj = (int64_t)bj * 16 + li;
-    double cval[4];
+    for (int s2 = 0; s2 < 4; ++s2) {
+        const int64_t ia = (int64_t)bi * 64 + s2 * 16 + li, ib = (int64_t)bj * 64 + s2 * 16 + li;
+        va[s2] = ia < k;
+        vb[s2] = ib < k;
+        pa[s2] = cen + (va[s2] ? ia : 0) * n;
+        pb[s2] = cen + (vb[s2] ? ib : 0) * n;
+    }
+    dvec4 acc[4][4];
+    gram64_accumulate<double, AL>(pa, pb, va, vb, bi == bj, c0, c1, acc);
+    gram64_store_tile(acc, Dp + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * 4096);
+}
+
+// k_cos64_rows: one workgroup per tile (bi, bj).  Entry (i, j) is the sum of
+// the parts in part order (on a diagonal tile taken from the lower half,
+// (max, min)), normalised to |d| / (|c_i||c_j|) (a zero centroid has C(t,t) = 1
+// and C(t,j) = 0) and kept in LDS; thread t takes entries t, t + 256, ...
+// Then thread (row, quarter) sums 16 entries in column order and the four
+// quarters combine by a fixed butterfly: the row sums -> Sp[i][bj], and
+// (bi != bj) the column sums -> Sp[j][bi]; every Sp entry is written once.
+__global__ __launch_bounds__(256) void k_cos64_rows(const double *__restrict__ Dp, int parts,
+                                                    int64_t k, const double *__restrict__ nrm,
+                                                    int ntc, double *__restrict__ Sp) {
+    __shared__ double c[64][65];
+    int bi, bj;
+    tile_of(blockIdx.x, ntc, &bi, &bj);
+    if (bi < 0) return;
+    const double *D = Dp + (int64_t)blockIdx.x * parts * 4096;
+#pragma unroll 2
+    for (int u = 0; u < 16; ++u) {
+        const int e0 = (int)threadIdx.x + 256 * u;
+        const int row = e0 >> 6, col = e0 & 63;
+        const int e = (bi == bj && col > row) ? col * 64 + row : e0;
+        // parts in order, eight loads issued at a time
+        double d = 0.0;
+        int p = 0;
+        for (; p + 8 <= parts; p += 8) {
+            double t[8];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double d = ((red[0][lane][r] + red[1][lane][r]) + red[2][lane][r]) + red[3][lane][r];
-        const int64_t ii = (int64_t)bi * 16 + (lane >> 4) + 4 * r;
-        double c = 0.0;
+            for (int q = 0; q < 8; ++q) t[q] = D[(int64_t)(p + q) * 4096 + e];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) d += t[q];
+        }
+        for (; p < parts; ++p) d += D[(int64_t)p * 4096 + e];
+        const int64_t ii = (int64_t)bi * 64 + row, jj = (int64_t)bj * 64 + col;
+        double v = 0.0;
         if (ii < k && jj < k) {
             const double ni = nrm[ii], nj = nrm[jj];
-            if (ni == 0.0 || nj == 0.0) c = (ii == jj) ? 1.0 : 0.0;
-            else c = fabs(d) / (ni * nj);
+            if (ni == 0.0 || nj == 0.0) v = (ii == jj) ? 1.0 : 0.0;
+            else v = fabs(d) / (ni * nj);
         }
-        cval[r] = c;
+        c[row][col] = v;
     }
-    // row sums: the 16 lanes of a lane group hold one row's 16 columns
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double rs = group_sum(cval[r], 16);
-        const int64_t ii = (int64_t)bi * 16 + (lane >> 4) + 4 * r;
-        if (li == 0 && ii < k) Sp[ii * ntc + bj] = rs;
-    }
+    const int row = threadIdx.x >> 2, qt = threadIdx.x & 3;
+    const int64_t ii = (int64_t)bi * 64 + row;
+    __syncthreads();
+    double rs = 0.0;
+    for (int u = 0; u < 16; ++u) rs += c[row][qt * 16 + u];
+    rs += __shfl_xor(rs, 1, 64);
+    rs += __shfl_xor(rs, 2, 64);
+    if (qt == 0 && ii < k) Sp[ii * ntc + bj] = rs;
     if (bi != bj) {
-        // column sums: registers r, then lane groups (xor 16, 32)
-        double cs = ((cval[0] + cval[1]) + cval[2]) + cval[3];
-        cs += __shfl_xor(cs, 16, 64);
-        cs += __shfl_xor(cs, 32, 64);
-        if (lane < 16 && jj < k) Sp[jj * ntc + bi] = cs;
+        // thread (column, quarter): rows qt*16 .. qt*16+15 of that column
+        const int col = threadIdx.x >> 2;
+        const int64_t jj = (int64_t)bj * 64 + col;
+        double cs = 0.0;
+        for (int u = 0; u < 16; ++u) cs += c[qt * 16 + u][col];
+        cs += __shfl_xor(cs, 1, 64);
+        cs += __shfl_xor(cs, 2, 64);
+        if (qt == 0 && jj < k) Sp[jj * ntc + bi] = cs;
     }
 }
 
@@ -530,19 +564,54 @@ __global__ __launch_bounds__(1024) void k_proposal(const double *__restrict__ pb
     }
 }
 
+// Column parts of the centroid Gram: the count P (at most 32, parts of at
+// least 256 columns, at most 4096 partial tiles) that spends the fewest
+// workgroup rounds per unit of work, ceil(tiles P / ncu) / P (one workgroup
+// per CU at a time); each part a multiple of 64 columns.
+void cos_parts(int64_t k, int64_t n, int ncu, int64_t *parts, int64_t *pw) {
+    const int64_t ntc = (k + 63) / 64, tiles = ntc * (ntc + 1) / 2;
+    int64_t pmax = 32;
+    if (pmax > n / 256) pmax = n / 256;
+    if (pmax > 4096 / tiles) pmax = 4096 / tiles;
+    if (pmax < 1) pmax = 1;
+    int64_t best = 1;
+    for (int64_t p = 2; p <= pmax; ++p) {
+        // rounds(p) / p < rounds(best) / best, in integers
+        const int64_t rp = (tiles * p + ncu - 1) / ncu, rb = (tiles * best + ncu - 1) / ncu;
+        if (rp * best < rb * p) best = p;
+    }
+    const int64_t w = ((n + best - 1) / best + 63) / 64 * 64;
+    *pw = w;
+    *parts = (n + w - 1) / w;
+}
+
+int64_t setup_proposal_scratch(int64_t k, int64_t n, int ncu) {
+    int64_t parts, pw;
+    cos_parts(k, n, ncu, &parts, &pw);
+    const int64_t ntc = (k + 63) / 64, tiles = ntc * (ntc + 1) / 2;
+    return k * n + k + k * ntc + tiles * parts * 4096;
+}
+
+// scratch: cen (k x n), nrm (k), Sp (k x ntc), then the Gram parts
 hipError_t launch_proposal_from_centroids(const rorbk_handle_s *h, double *cen, double *nrm,
                                           double *Sp, hipStream_t s) {
     const Layout &L = h->L;
     hipLaunchKernelGGL(k_rownorm, dim3((unsigned)L.k), dim3(256), 0, s, cen, L.n, nrm);
-    const int64_t ntc = (L.k + 15) / 16;
+    const int64_t ntc = (L.k + 63) / 64;
     const int64_t tiles = ntc * (ntc + 1) / 2;
+    int64_t parts, pw;
+    cos_parts(L.k, L.n, h->ncu, &parts, &pw);
+    double *Dp = Sp + L.k * ntc;
     const bool al = (L.n % 2) == 0;   // 16-byte rows of the FP64 centroid matrix
+    const dim3 grid((unsigned)tiles, (unsigned)parts);
     if (al)
-        hipLaunchKernelGGL(k_cos_mfma<true>, dim3((unsigned)tiles), dim3(256), 0, s, cen, L.k, L.n,
-                           nrm, Sp, ntc);
+        hipLaunchKernelGGL(k_cos64_part<true>, grid, dim3(256), 0, s, cen, L.k, L.n, pw, (int)ntc,
+                           Dp);
     else
-        hipLaunchKernelGGL(k_cos_mfma<false>, dim3((unsigned)tiles), dim3(256), 0, s, cen, L.k,
-                           L.n, nrm, Sp, ntc);
+        hipLaunchKernelGGL(k_cos64_part<false>, grid, dim3(256), 0, s, cen, L.k, L.n, pw,
+                           (int)ntc, Dp);
+    hipLaunchKernelGGL(k_cos64_rows, dim3((unsigned)tiles), dim3(256), 0, s, Dp, (int)parts, L.k,
+                       nrm, (int)ntc, Sp);
     hipLaunchKernelGGL(k_proposal_rows, dim3((unsigned)((L.k + 3) / 4)), dim3(256), 0, s, Sp, ntc,
                        L.k, L.n, h->d_S, h->d_pbar);
     hipLaunchKernelGGL(k_proposal, dim3(1), dim3(1024), 0, s, h->d_pbar, L.k, h->d_W);
@@ -612,7 +681,7 @@ __global__ __launch_bounds__(256) void k_block_gram_mfma(const T *__restrict__ A
 }
 
 // The same block Grams on 64 x 64 tiles (gram_tiles.h) for blocks of at least
-// GRAM64_MIN_K rows: grid x = lower 64 x 64 tiles of the largest block, grid
+// 48 rows: grid x = lower 64 x 64 tiles of the largest block, grid
 // y = blocks; each workgroup sums its tile over all n columns, with the
 // values of the 16 x 16 tile kernel.
 template <typename T, bool AL>
@@ -759,7 +828,9 @@ hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A, i
     double *Gs = nullptr;
     hipError_t e = hipMallocAsync((void **)&Gs, sizeof(double) * (size_t)(kp * L.k), s);
     if (e != hipSuccess) return e;
-    const bool t64 = L.bmax >= GRAM64_MIN_K;
+    // 64 x 64 tiles once a block fills most of one (48 rows: the 16 x 16 form
+    // has as many products then, each a dependent MFMA chain of its own)
+    const bool t64 = L.bmax >= 48;
     const int nt = (int)(t64 ? (L.bmax + 63) / 64 : (L.bmax + 15) / 16);
     dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)L.k);
 #define RORBK_BG(T)                                                                             \

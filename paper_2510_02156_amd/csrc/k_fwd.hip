@@ -16,6 +16,7 @@
 // products, and x3 = x0 + A_1^T y1 + A_2^T y2 + A_3^T y3 is one more pass.  The
 // same iterate results in exact arithmetic; the roundings differ from three
 // separate steps.
+#include "ldl_blk.h"
 #include "rorbk_device.h"
 #include "xgram.h"
 
@@ -704,7 +705,7 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_samp3(FwdSamp3P p) {
 // ------------------------------------------------------- chain step kernel --
 // The rest of iteration it after the chain form's Grams (k_gram_chain), in one
 // launch over the column slabs (one sub-slab each): in every workgroup wave 0
-// solves the greedy system (G + lambda I) y = r_I (ldl_wave64 on the summed
+// solves the greedy system (G + lambda I) y = r_I (ldl_blk64 on the summed
 // Gram chunks; every workgroup forms the same y) while waves 1-7 sum C into
 // LDS and load the three sampled steps' matrices into registers, so that their
 // memory latency is spent during the factorisation.  Then
@@ -738,7 +739,7 @@ struct FwdChainP {
 constexpr int CHN = 4;                       // most column chunks of G and C
 constexpr int FC_T = FWD_T - 64;             // threads of waves 1-7
 constexpr int FILL2 = (3 * FWD_B * FWD_B + FC_T - 1) / FC_T;   // H2, G32, H3 entries per thread
-constexpr int LA = 64 * 65 / 2 + 64 * 65 + 2 * MAXB;          // LDS doubles: Gp | Lc | colbuf
+constexpr int LA = 64 * 65 + 2 * 64;                          // LDS doubles: work matrix | colbuf
 
 template <typename T, typename V, bool AL, int RN>
 __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
@@ -751,7 +752,7 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
     V *__restrict__ x = (V *)p.x;
     const int tid = threadIdx.x;
     const int K = p.K, KP = K * (K + 1) / 2;
-    // LDS: region a holds the factorisation (packed Gram, L, column buffers),
+    // LDS: region a holds the factorisation (the padded system, then L; column buffers),
     // then z, y and the update's row sums; region b holds C, then H2, G32, H3
     __shared__ double lds_a[LA];
     __shared__ double lds_b[3 * FWD_B * LDM];
@@ -760,7 +761,7 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
     __shared__ V s_x[SWC];
     __shared__ int32_t s_row[64 + 3 * FWD_B], s_slot[64 + 3 * FWD_B];
     __shared__ int s_ok;
-    double *Gp = lds_a, *Lc = lds_a + 64 * 65 / 2, *colbuf = Lc + 64 * 65;
+    double *Lc = lds_a, *colbuf = Lc + 64 * 65;
     double *s_z = lds_a, *s_y = lds_a + 256;
     V (*s_red)[SWC] = reinterpret_cast<V (*)[SWC]>(lds_a + 1024);
 
@@ -779,25 +780,25 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
             }
         const double ri = p.rI[tid < K ? tid : 0];
         if (stop) return;
+        // the padded system straight into the work matrix (lambda on the
+        // diagonal, the identity beyond K)
 #pragma unroll
         for (int u = 0; u < NU0; ++u) {
             const int f = tid + u * FWD_T;
             double gs = gt[0][u];
 #pragma unroll
             for (int c = 1; c < CHN; ++c) gs += (c < p.nch) ? gt[c][u] : 0.0;
-            if (f < KP) Gp[f] = gs;
+            if (f < 64 * 65 / 2) lb_put(Lc, f, gs, K, p.lambda);
         }
-        if (tid < K) s_yk[tid] = ri;
+        if (tid < 64) s_yk[tid] = (tid < K) ? ri : 0.0;
     }
-    __syncthreads();
-    if (tid < K) Gp[pk(tid, tid)] += p.lambda;
     __syncthreads();
 
     // --- phase 1: wave 0 factors (nothing else is live across it; the
     // wave index is made scalar so that both branches are real jumps) ...
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (wv == 0) {
-        const bool ok = ldl_wave64(Gp, s_yk, K, colbuf, Lc);
+        const bool ok = ldl_blk64(Lc, s_yk, K, colbuf);
         if (tid == 0) {
             s_ok = ok ? 1 : 0;
             if (!ok) {

@@ -838,8 +838,7 @@ int ror_bk_setup(const rorbk_matrix *A, int64_t block_rows, double lambda, void 
         return bail(fail(RORBK_ERR_HIP, "partition launch failed"));
     // centroid cosines and the proposal
     {
-        const int64_t ntile = (k + 15) / 16;
-        const int64_t len = k * L.n + k + k * ntile;
+        const int64_t len = setup_proposal_scratch(k, L.n, h->ncu);
         double *scratch = nullptr;
         rc = dalloc(&scratch, (size_t)len);
         if (rc) return bail(rc);

@@ -201,6 +201,9 @@ hipError_t launch_setup_proposal_dense(const rorbk_handle_s *h, const void *A,
 hipError_t launch_block_inverses_dense(const rorbk_handle_s *h, const void *A,
                                        int dt, int aligned, int32_t *d_fail,
                                        hipStream_t s);
+// doubles of device scratch the proposal setup needs (centroids, norms, row
+// sums, centroid Gram parts)
+int64_t setup_proposal_scratch(int64_t k, int64_t n, int ncu);
 hipError_t launch_proposal_from_centroids(const rorbk_handle_s *h, double *cen, double *nrm,
                                           double *Sp, hipStream_t s);
 // stored inverses (G_t + lambda I)^{-1} from packed block Grams Gs[t][kp]
