@@ -288,15 +288,41 @@ __device__ __forceinline__ void st32(double (*D)[TB + 1], dvec4 v) {
     st16(&D[R * 16][C * 16], TB + 1, v, 1.0);
 }
 
+// 32 x 32 tiles on 256 threads: thread t takes entries t + 256 u (u < 4); the
+// four loads of a tile are issued before any of them is stored to LDS.
+constexpr int TU = TB * TB / 256;
+
+__device__ __forceinline__ void tile_fetch(const double *src, int ld, double (&v)[TU]) {
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+        const int e = (int)threadIdx.x + 256 * u;
+        v[u] = src[(int64_t)(e / TB) * ld + e % TB];
+    }
+}
+
+__device__ __forceinline__ void tile_put(double (*S)[TB + 1], const double (&v)[TU]) {
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+        const int e = (int)threadIdx.x + 256 * u;
+        S[e / TB][e % TB] = v[u];
+    }
+}
+
 __device__ __forceinline__ void tile_load(double (*S)[TB + 1], const double *src, int ld) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
-        S[e / TB][e % TB] = src[(int64_t)(e / TB) * ld + e % TB];
+    double v[TU];
+    tile_fetch(src, ld, v);
+    tile_put(S, v);
 }
 
 // transposed: S[c][r] = src[r][c]
 __device__ __forceinline__ void tile_load_t(double (*S)[TB + 1], const double *src, int ld) {
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x)
-        S[e % TB][e / TB] = src[(int64_t)(e / TB) * ld + e % TB];
+    double v[TU];
+    tile_fetch(src, ld, v);
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+        const int e = (int)threadIdx.x + 256 * u;
+        S[e % TB][e / TB] = v[u];
+    }
 }
 
 __device__ __forceinline__ void tile_store(double *dst, int ld, const double (*S)[TB + 1]) {
@@ -335,13 +361,23 @@ __global__ __launch_bounds__(256) void k_big_chol_col(double *__restrict__ G,
     const bool rhs_slot = J >= P;
     double *Gb = G + (int64_t)bt * mstride;
     double *Lb = Lf + (int64_t)bt * mstride;
-    if (p >= 0) {
-        const double *Wp = W + ((int64_t)bt * P + p) * TB * TB;
-        for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) sW[e / TB][e % TB] = Wp[e];
-        tile_load(sA, Gb + (int64_t)(I * TB) * ld + p * TB, ld);
-        if (J != I) tile_load(sB, Gb + (int64_t)(J * TB) * ld + p * TB, ld);
+    // every tile this workgroup reads is fetched before any is stored to LDS
+    // (one memory latency instead of one per tile)
+    {
+        double vw[TU], va[TU], vb[TU], vt[TU];
+        if (p >= 0) {
+            tile_fetch(W + ((int64_t)bt * P + p) * TB * TB, TB, vw);
+            tile_fetch(Gb + (int64_t)(I * TB) * ld + p * TB, ld, va);
+            if (J != I) tile_fetch(Gb + (int64_t)(J * TB) * ld + p * TB, ld, vb);
+        }
+        if (!rhs_slot) tile_fetch(Gb + (int64_t)(I * TB) * ld + J * TB, ld, vt);
+        if (p >= 0) {
+            tile_put(sW, vw);
+            tile_put(sA, va);
+            if (J != I) tile_put(sB, vb);
+        }
+        if (!rhs_slot) tile_put(sT, vt);
     }
-    if (!rhs_slot) tile_load(sT, Gb + (int64_t)(I * TB) * ld + J * TB, ld);
     __syncthreads();
     if (p >= 0) {
         const dvec4 li = mm32_abt(sA, sW);

@@ -565,13 +565,14 @@ __global__ __launch_bounds__(1024) void k_proposal(const double *__restrict__ pb
 }
 
 // Column parts of the centroid Gram: the count P (at most 32, parts of at
-// least 256 columns, at most 4096 partial tiles) that spends the fewest
+// least 512 columns so that the per-workgroup reduction and store stay small
+// beside the products, at most 4096 partial tiles) that spends the fewest
 // workgroup rounds per unit of work, ceil(tiles P / ncu) / P (one workgroup
 // per CU at a time); each part a multiple of 64 columns.
 void cos_parts(int64_t k, int64_t n, int ncu, int64_t *parts, int64_t *pw) {
     const int64_t ntc = (k + 63) / 64, tiles = ntc * (ntc + 1) / 2;
     int64_t pmax = 32;
-    if (pmax > n / 256) pmax = n / 256;
+    if (pmax > n / 512) pmax = n / 512;
     if (pmax > 4096 / tiles) pmax = 4096 / tiles;
     if (pmax < 1) pmax = 1;
     int64_t best = 1;
@@ -580,7 +581,8 @@ void cos_parts(int64_t k, int64_t n, int ncu, int64_t *parts, int64_t *pw) {
         const int64_t rp = (tiles * p + ncu - 1) / ncu, rb = (tiles * best + ncu - 1) / ncu;
         if (rp * best < rb * p) best = p;
     }
-    const int64_t w = ((n + best - 1) / best + 63) / 64 * 64;
+    int64_t w = ((n + best - 1) / best + 63) / 64 * 64;
+    if (w < 64) w = 64;
     *pw = w;
     *parts = (n + w - 1) / w;
 }
