@@ -25,7 +25,29 @@ constexpr int SEG = 2048;  // columns of one residual segment (x kept in VGPRs)
 // the next iteration's sampled blocks (xgram.h): MFMA work on a few rows that
 // sits in cache, done while the pass streams A (those workgroups of the other
 // segment rows leave at once).
-template <typename T, typename V, bool AL, int ROWS, int SW>
+//
+// SH (rows whose start is 16-byte aligned or half a vector past it: a 16-byte
+// aligned matrix with a row stride of 4 mod 8 elements, BF16 rows of 1000
+// bytes for instance): a row that starts half a vector off is read with the
+// same aligned 16-byte loads moved back by half a vector, against a second
+// copy of x shifted the same way; the vector that would pass the matrix's
+// last element takes the element-wise path, and elements outside the row's
+// columns are cleared.  The other rows take the aligned form.
+template <typename T>
+__device__ __forceinline__ uvec4 clear_outside(uvec4 w, int64_t c, int64_t n) {
+    constexpr int VW = Tr<T>::VW;
+    static_assert(sizeof(T) == 2, "shifted rows: 16-bit values");
+#pragma unroll
+    for (int e = 0; e < VW / 2; ++e) {
+        const int64_t c0 = c + 2 * e, c1 = c0 + 1;
+        const uint32_t lo = (c0 >= 0 && c0 < n) ? 0x0000ffffu : 0u;
+        const uint32_t hi = (c1 >= 0 && c1 < n) ? 0xffff0000u : 0u;
+        w[e] &= (lo | hi);
+    }
+    return w;
+}
+
+template <typename T, typename V, bool AL, int ROWS, int SW, bool SH = false>
 __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
                                                      const V *__restrict__ x,
@@ -50,6 +72,17 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 #pragma unroll
         for (int e = 0; e < VW; ++e) xr[s][e] = (col + e < n) ? x[col + e] : (V)0;
     }
+    V xs[SH ? NVL : 1][VW];   // x moved back by half a vector (SH)
+    if constexpr (SH) {
+#pragma unroll
+        for (int s = 0; s < NVL; ++s) {
+            const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW - VW / 2;
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+                xs[s][e] = (col + e >= 0 && col + e < n) ? x[col + e] : (V)0;
+        }
+    }
+    const int64_t last = (m - 1) * ld + n;   // one past the matrix's last element
     const int64_t bx = (int64_t)blockIdx.x - side.jobs;
     const int64_t nwaves = (int64_t)(gridDim.x - side.jobs) * 4;
     const int64_t stride = nwaves * ROWS;
@@ -59,21 +92,42 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
             const int64_t row = (i + rr < m) ? i + rr : m - 1;
+            if constexpr (SH) {
+                // wave-uniform: does this row start half a vector off?
+                const int64_t sh = ((row * ld) & (VW - 1)) ? VW / 2 : 0;
 #pragma unroll
-            for (int s = 0; s < NVL; ++s) {
-                const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
-                raw[rr][s] = load_raw_nt_sel<T, AL>(A + row * ld, col, n, true, A + row * ld, c0);
+                for (int s = 0; s < NVL; ++s) {
+                    const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW - sh;
+                    uvec4 w;
+                    if (row * ld + col + VW <= last)
+                        w = __builtin_nontemporal_load(
+                            reinterpret_cast<const uvec4 *>(A + row * ld + col));
+                    else
+                        w = load_raw<T, false>(A + row * ld, col, n);
+                    raw[rr][s] = clear_outside<T>(w, col, n);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NVL; ++s) {
+                    const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
+                    raw[rr][s] = load_raw_nt_sel<T, AL>(A + row * ld, col, n, true, A + row * ld, c0);
+                }
             }
         }
 #pragma unroll
         for (int rr = 0; rr < ROWS; ++rr) {
             V acc = (V)0;
+            bool shifted = false;
+            if constexpr (SH) {
+                const int64_t row = (i + rr < m) ? i + rr : m - 1;
+                shifted = ((row * ld) & (VW - 1)) != 0;
+            }
 #pragma unroll
             for (int s = 0; s < NVL; ++s) {
                 V a[VW];
                 cvt_raw<T, V>(raw[rr][s], a);
 #pragma unroll
-                for (int e = 0; e < VW; ++e) acc = fmaT(a[e], xr[s][e], acc);
+                for (int e = 0; e < VW; ++e) acc = fmaT(a[e], shifted ? xs[s][e] : xr[s][e], acc);
             }
             const V sres = group_sum(acc, WAVE);
             if (lane == 0 && i + rr < m) axp[seg * m + i + rr] = (double)sres;
@@ -81,7 +135,7 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
     }
 }
 
-template <typename T, typename V, int ROWS, int SW>
+template <typename T, typename V, int ROWS, int SW, bool SH = false>
 static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligned,
                               const void *x, double *axp, const XgSide &side, hipStream_t s) {
     static_assert(SW == SEG || SW == 512 || SW == 1024, "segment width");
@@ -104,6 +158,12 @@ static hipError_t resid_typed(const rorbk_handle_s *h, const void *A, int aligne
     if (cap < 1) cap = 1;
     if (groups > cap) groups = cap;
     dim3 grid((unsigned)(groups + side.jobs), (unsigned)L.nseg);
+    if constexpr (SH) {
+        hipLaunchKernelGGL((k_resid_dense<T, V, false, ROWS, SW, true>), grid, dim3(256), 0, s,
+                           (const T *)A, L.ld, L.m, L.n, (const V *)x, axp,
+                           (const Ctrl *)h->d_ctrl, side);
+        return hipGetLastError();
+    }
     if (aligned)
         hipLaunchKernelGGL((k_resid_dense<T, V, true, ROWS, SW>), grid, dim3(256), 0, s, (const T *)A,
                            L.ld, L.m, L.n, (const V *)x, axp, (const Ctrl *)h->d_ctrl, side);
@@ -139,9 +199,17 @@ hipError_t launch_residual_dense_side(const rorbk_handle_s *h, const void *A, in
         if (n <= 1024) return resid_typed<float, float, 4, 1024>(h, A, aligned, x, axp, side, s);
         return resid_typed<float, float, 2, SEG>(h, A, aligned, x, axp, side, s);
     }
-    if (n <= 512) return resid_typed<bf16_t, float, 16, 512>(h, A, aligned, x, axp, side, s);
-    if (n <= 1024) return resid_typed<bf16_t, float, 8, 1024>(h, A, aligned, x, axp, side, s);
-    return resid_typed<bf16_t, float, 4, SEG>(h, A, aligned, x, axp, side, s);
+    // BF16 rows that start 16-byte aligned or half a vector past it (a
+    // 16-byte aligned matrix, row stride 4 mod 8 elements): the shifted form
+    const bool sh = !aligned && (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (h->L.ld & 7) == 4;
+    if (n <= 512)
+        return sh ? resid_typed<bf16_t, float, 16, 512, true>(h, A, aligned, x, axp, side, s)
+                  : resid_typed<bf16_t, float, 16, 512>(h, A, aligned, x, axp, side, s);
+    if (n <= 1024)
+        return sh ? resid_typed<bf16_t, float, 8, 1024, true>(h, A, aligned, x, axp, side, s)
+                  : resid_typed<bf16_t, float, 8, 1024>(h, A, aligned, x, axp, side, s);
+    return sh ? resid_typed<bf16_t, float, 4, SEG, true>(h, A, aligned, x, axp, side, s)
+              : resid_typed<bf16_t, float, 4, SEG>(h, A, aligned, x, axp, side, s);
 }
 
 }  // namespace rorbk

@@ -426,102 +426,4 @@ __device__ __forceinline__ double bcast64(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Single-wave solve (G) y = r for K <= 64, the workgroup's other waves having
-// left (no block barrier inside).  LDL^T with unit L by right-looking
-// elimination: lane i keeps row i of G in registers (entries j <= i are live).
-// At step k the pivot d_k comes from lane k by readlane, lane i forms
-// l_ik = g_ik / d_k, updates its row g_ij -= l_ik g_jk (j > k) with column k
-// read from LDS, and the forward substitution z_i -= l_ik z_k.  Column k+1 is
-// published to LDS right after its own update, so the write overlaps the rest
-// of the step.  1 / d_k is the hardware reciprocal r0 refined by Newton's
-// iteration, r1 = r0 (2 - d r0), with the second step folded into its uses
-// (l = g r1 + g r1 (1 - d r1)); the next pivot is formed straight from this
-// one, d_{k+1} = g_{k+1,k+1} - g_{k+1,k}^2 / d_k, so the chain from pivot to
-// pivot is two broadcasts and five dependent operations.  The factor (l_ik
-// below the diagonal, d_k on it) is kept column by column in Lc[k * 65 + i]
-// for the backward pass y_k = z_k / d_k - sum_{i>k} l_ik y_i.  The steps are
-// generated with compile-time k so that every register index is static.
-template <int N, int k>
-__device__ __forceinline__ void ldl_step(double (&a)[N], double &zi, double &dnext, int lane,
-                                         double *colbuf, double *Lc, bool &ok) {
-    const double *col = colbuf + (k & 1) * 64;
-    double *nxt = colbuf + ((k + 1) & 1) * 64;
-    const double d = bcast64(dnext, k);
-    ok = ok && (d > 0.0);
-    const double r0 = __builtin_amdgcn_rcp(d);
-    const double e0 = __builtin_fma(-d, r0, 1.0);
-    const double r1 = __builtin_fma(r0, e0, r0);
-    const double e1 = __builtin_fma(-d, r1, 1.0);
-    const double akk = a[k];
-    const double m1 = akk * r1;
-    const double c = __builtin_fma(m1, e1, m1);
-    if constexpr (k + 1 < N) {
-        const double t = akk * akk;
-        const double tr1 = t * r1;
-        const double u = __builtin_fma(-t, r1, a[k + 1]);
-        dnext = __builtin_fma(-tr1, e1, u);
-    }
-    const double zk = bcast64(zi, k);
-    zi = (lane > k) ? __builtin_fma(-c, zk, zi) : zi;
-    Lc[k * 65 + lane] = (lane > k) ? c : d;
-    // column k (rows > k) into registers first, then the row update
-    double cv[N];
-#pragma unroll
-    for (int j = k + 1; j < N; ++j) cv[j] = col[j];
-    if constexpr (k + 1 < N) {
-        a[k + 1] = __builtin_fma(-c, cv[k + 1], a[k + 1]);
-        nxt[lane] = a[k + 1];
-    }
-#pragma unroll
-    for (int j = k + 2; j < N; ++j) a[j] = __builtin_fma(-c, cv[j], a[j]);
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <int N, int... Ks>
-__device__ __forceinline__ void ldl_steps(std::integer_sequence<int, Ks...>, double (&a)[N],
-                                          double &zi, int lane, double *colbuf, double *Lc,
-                                          bool &ok) {
-    double dnext = a[0];
-    (ldl_step<N, Ks>(a, zi, dnext, lane, colbuf, Lc, ok), ...);
-}
-
-// The system is padded to N x N (N = 32 or 64, K <= N) with the identity
-// beyond K (zero right-hand side), which leaves the leading K x K factor and
-// solution unchanged and keeps the N unrolled steps free of branches; lanes
-// from N on carry no row and their values are never used.
-template <int N>
-__device__ __forceinline__ bool ldl_wave(const double *Gp, double *z, int K, double *colbuf /* 2*64 */,
-                                double *Lc /* 64*65 */) {
-    const int lane = threadIdx.x & 63;
-    double a[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        // every lane reads an entry of its own packed row (no read behind a
-        // branch), the upper part is then replaced by zeros
-        const double gv = Gp[pk(lane, j <= lane ? j : lane)];
-        a[j] = (lane < K && j < K) ? ((j <= lane) ? gv : 0.0) : (j == lane ? 1.0 : 0.0);
-    }
-    double zi = (lane < K) ? z[lane] : 0.0;
-    colbuf[lane] = a[0];
-    __builtin_amdgcn_wave_barrier();
-    bool ok = true;
-    ldl_steps<N>(std::make_integer_sequence<int, N>{}, a, zi, lane, colbuf, Lc, ok);
-    if (!ok) return false;
-    // backward substitution, column oriented
-    double w = zi / Lc[lane * 65 + lane];
-    for (int k = K - 1; k >= 0; --k) {
-        const double yk = bcast64(w, k);
-        if (lane < k) w = __builtin_fma(-Lc[lane * 65 + k], yk, w);
-    }
-    if (lane < K) z[lane] = w;
-    __builtin_amdgcn_wave_barrier();
-    return true;
-}
-
-// K <= 64 on one wave: the 32-row form when it suffices.
-__device__ __forceinline__ bool ldl_wave64(const double *Gp, double *z, int K, double *colbuf,
-                                  double *Lc) {
-    return (K <= 32) ? ldl_wave<32>(Gp, z, K, colbuf, Lc) : ldl_wave<64>(Gp, z, K, colbuf, Lc);
-}
-
 }  // namespace rorbk

@@ -108,3 +108,28 @@ def test_refine_requires_master():
     with pytest.raises(P.RorBkError) as e:
         sol.solve(dev(s["b"]), seed=1, tol=1e-8, max_iters=10, refine=True)
     assert e.value.code == P.RORBK_ERR_INVALID_ARG
+
+
+# BF16 rows whose stride is 4 mod 8 elements (rows start 16-byte aligned or
+# half a vector past it, alternately): the residual pass reads them with
+# aligned loads moved back by half a vector; the last row's end takes the
+# element-wise path.  Strides 0 mod 8 and 2 mod 8 take the other two forms.
+@pytest.mark.parametrize("m,n,br", [(1, 500, 1), (3, 12, 2), (7, 500, 3), (130, 300, 16),
+                                    (40, 1020, 8), (129, 2500, 32), (65, 4100, 16),
+                                    (33, 130, 8), (17, 512, 4)])
+def test_bf16_residual_row_strides(m, n, br):
+    rng = np.random.default_rng(m * 7919 + n)
+    A = rng.standard_normal((m, n))
+    Av = bf16_values(A)
+    x = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    b = rng.standard_normal(m).astype(np.float32).astype(np.float64)
+    sol = P.Solver(bf16_tensor(A), br, 1e-3)
+    r, _, _ = sol.residual(dev(b, torch.float32), dev(x, torch.float32))
+    rr = b - Av @ x
+    scale = np.abs(Av) @ np.abs(x) + np.abs(b)
+    # FP32 products summed in FP32 (each lane in column order, then a six-level
+    # butterfly), then r rounded to FP32: at most n + 8 roundings per term
+    bound = (n + 8) * 2.0 ** -24 * scale * 1.01
+    err = np.abs(host(r) - rr)
+    print(f"bf16 residual m={m} n={n}: max err / bound {np.max(err / bound):.3f}", flush=True)
+    assert np.all(err <= bound)
