@@ -474,38 +474,50 @@ __global__ __launch_bounds__(256) void k_cos64_rows(const double *__restrict__ D
                                                     int64_t k, const double *__restrict__ nrm,
                                                     int ntc, double *__restrict__ Sp) {
     __shared__ double c[64][65];
+    __shared__ double s_n[128];   // |c_i| of the tile's rows, then of its columns
     int bi, bj;
     tile_of(blockIdx.x, ntc, &bi, &bj);
     if (bi < 0) return;
+    if (threadIdx.x < 128) {
+        const int64_t g = (threadIdx.x < 64) ? (int64_t)bi * 64 + threadIdx.x
+                                             : (int64_t)bj * 64 + threadIdx.x - 64;
+        s_n[threadIdx.x] = (g < k) ? nrm[g] : 0.0;
+    }
     const double *D = Dp + (int64_t)blockIdx.x * parts * 4096;
-#pragma unroll 2
+    // the sixteen entries of this thread summed over the parts in part
+    // order, the sixteen loads of a part issued together
+    double d[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) d[u] = 0.0;
+    for (int p = 0; p < parts; ++p) {
+        double t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int e0 = (int)threadIdx.x + 256 * u;
+            const int row = e0 >> 6, col = e0 & 63;
+            const int e = (bi == bj && col > row) ? col * 64 + row : e0;
+            t[u] = D[(int64_t)p * 4096 + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) d[u] += t[u];
+    }
+    __syncthreads();
+#pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int e0 = (int)threadIdx.x + 256 * u;
         const int row = e0 >> 6, col = e0 & 63;
-        const int e = (bi == bj && col > row) ? col * 64 + row : e0;
-        // parts in order, eight loads issued at a time
-        double d = 0.0;
-        int p = 0;
-        for (; p + 8 <= parts; p += 8) {
-            double t[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) t[q] = D[(int64_t)(p + q) * 4096 + e];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) d += t[q];
-        }
-        for (; p < parts; ++p) d += D[(int64_t)p * 4096 + e];
         const int64_t ii = (int64_t)bi * 64 + row, jj = (int64_t)bj * 64 + col;
         double v = 0.0;
         if (ii < k && jj < k) {
-            const double ni = nrm[ii], nj = nrm[jj];
+            const double ni = s_n[row], nj = s_n[64 + col];
             if (ni == 0.0 || nj == 0.0) v = (ii == jj) ? 1.0 : 0.0;
-            else v = fabs(d) / (ni * nj);
+            else v = fabs(d[u]) / (ni * nj);
         }
         c[row][col] = v;
     }
+    __syncthreads();
     const int row = threadIdx.x >> 2, qt = threadIdx.x & 3;
     const int64_t ii = (int64_t)bi * 64 + row;
-    __syncthreads();
     double rs = 0.0;
     for (int u = 0; u < 16; ++u) rs += c[row][qt * 16 + u];
     rs += __shfl_xor(rs, 1, 64);
