@@ -951,21 +951,21 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
         if (h == 0 && ir < rows) s_z[rg * FWD_B + ir] -= d;
     }
     // the update's rows load during the rest of the chain
-    auto urow = [&](int r, int64_t *row, int *slot) -> bool {
-        const int qq = g + G * r;
-        const bool ok = qq < nrows;
-        *row = ok ? (int64_t)((volatile int32_t *)s_row)[qq] : 0;
-        *slot = ok ? ((volatile int32_t *)s_slot)[qq] : 0;
-        return ok;
-    };
     const int64_t col = c0 + (int64_t)v * VW;
     uvec4 ua[RN];
+    {
+        // every row index first (LDS), then every load, so that the loads
+        // do not wait on one LDS read each
+        int32_t rw[RN];
 #pragma unroll
-    for (int r = 0; r < RN; ++r) {
-        int64_t row;
-        int slot;
-        const bool ok = urow(r, &row, &slot);
-        ua[r] = load_raw_sel<T, AL>(A + row * p.ld, col, c1, ok, A, c0);
+        for (int r = 0; r < RN; ++r) {
+            const int qq = g + G * r;
+            rw[r] = (qq < nrows) ? s_row[qq] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < RN; ++r)
+            ua[r] = load_raw_sel<T, AL>(A + (int64_t)rw[r] * p.ld, col, c1, g + G * r < nrows, A,
+                                        c0);
     }
     __syncthreads();
     // y2 = H2 z2
@@ -991,16 +991,25 @@ __global__ __launch_bounds__(FWD_T) void k_fwd_chain(FwdChainP p) {
     V acc[VW];
 #pragma unroll
     for (int e = 0; e < VW; ++e) acc[e] = (V)0;
+    {
+        // the slots, then their y, then the products (no LDS read waits on
+        // another inside the loop)
+        int32_t sl[RN];
 #pragma unroll
-    for (int r = 0; r < RN; ++r) {
-        int64_t row;
-        int slot;
-        const bool ok = urow(r, &row, &slot);
-        const V yr = ok ? (V)s_y[slot] : (V)0;
-        V av[VW];
-        cvt_raw<T, V>(ua[r], av);
+        for (int r = 0; r < RN; ++r) {
+            const int qq = g + G * r;
+            sl[r] = (qq < nrows) ? s_slot[qq] : -1;
+        }
+        V yv[RN];
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] = fmaT(av[e], yr, acc[e]);
+        for (int r = 0; r < RN; ++r) yv[r] = (sl[r] >= 0) ? (V)s_y[sl[r] >= 0 ? sl[r] : 0] : (V)0;
+#pragma unroll
+        for (int r = 0; r < RN; ++r) {
+            V av[VW];
+            cvt_raw<T, V>(ua[r], av);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] = fmaT(av[e], yv[r], acc[e]);
+        }
     }
 #pragma unroll
     for (int e = 0; e < VW; ++e) s_red[g][v * VW + e] = acc[e];
