@@ -202,7 +202,7 @@ __device__ __forceinline__ void lb_back_blocks(std::integer_sequence<int, Ps...>
     (lb_back_block<NP - 1 - Ps>(S, wb), ...);
 }
 
-// Single-wave solve of the padded N x N system (N = 16, 32 or 64, K <= N) held
+// Single-wave solve of the padded N x N system (N = 16, 32 or 64) held
 // in S (the 64 x 65 work matrix, lower triangle of rows 0 .. N - 1, filled by
 // lb_put: the Gram with lambda on the diagonal, the identity from row K on),
 // right-hand side in z (entries K .. N - 1 zero; overwritten by y), colbuf
@@ -213,7 +213,7 @@ __device__ __forceinline__ void lb_back_blocks(std::integer_sequence<int, Ps...>
 // workgroup's other waves may be elsewhere.  Returns false if a pivot is not
 // positive.
 template <int N>
-__device__ __forceinline__ bool ldl_blk(double *S, double *z, int K, double *colbuf) {
+__device__ __forceinline__ bool ldl_blk(double *S, double *z, double *colbuf) {
     const int lane = threadIdx.x & 63;
     bool ok = true;
     lb_panels<N>(std::make_integer_sequence<int, N / 16>{}, S, z, colbuf, ok);
@@ -221,15 +221,14 @@ __device__ __forceinline__ bool ldl_blk(double *S, double *z, int K, double *col
     if (lane < N) z[lane] = z[lane] / S[lane * LB_RS + lane];
     __builtin_amdgcn_wave_barrier();
     lb_back_blocks(std::make_integer_sequence<int, N / 16>{}, S, z);
-    (void)K;
     return true;
 }
 
 // K <= 64 on one wave: the smallest padded size that holds the system.
 __device__ __forceinline__ bool ldl_blk64(double *S, double *z, int K, double *colbuf /* 2 x 64 */) {
-    if (K <= 16) return ldl_blk<16>(S, z, K, colbuf);
-    if (K <= 32) return ldl_blk<32>(S, z, K, colbuf);
-    return ldl_blk<64>(S, z, K, colbuf);
+    if (K <= 16) return ldl_blk<16>(S, z, colbuf);
+    if (K <= 32) return ldl_blk<32>(S, z, colbuf);
+    return ldl_blk<64>(S, z, colbuf);
 }
 
 }  // namespace rorbk
