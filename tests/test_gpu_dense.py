@@ -135,6 +135,24 @@ def test_replay_trajectory_fp64(m, n, br, lam, cond):
     np.testing.assert_allclose(rec["rrn"], ref["rrn_hist"], rtol=1e-9)
 
 
+# Greedy sets at the edges of the panel solve's padded sizes (16, 32 and 64
+# rows: sets of 17, 32, 33, 48 and 63 rows) through the chain form's greedy
+# solve, replayed against the oracle.
+@pytest.mark.parametrize("m,n,br", [(17 * 40, 300, 17), (32 * 40, 300, 32), (33 * 40, 257, 33),
+                                    (48 * 30, 400, 48), (63 * 30, 500, 63)])
+def test_replay_greedy_set_sizes(m, n, br):
+    s = make(m, n, 1e3)
+    iters = 40
+    ref = O.solve(s["A"], br, 1e-3, s["b"], seed=6, max_iters=iters)
+    sol = P.Solver(dev(s["A"]), br, 1e-3)
+    assert sol.K == br
+    sol.set_replay(ref["tau"], ref["I"], iters)
+    x, info = sol.solve(dev(s["b"]), seed=0, tol=0.0, max_iters=iters, replay=True)
+    e = rel(host(x), ref["x"])
+    print(f"replay K={br}: rel err {e:.3e}", flush=True)
+    assert e < 1e-10
+
+
 @pytest.mark.parametrize("m,n,br,lam,cond", SHAPES[:4])
 def test_free_running_matches_oracle(m, n, br, lam, cond):
     """Free running with the oracle's W: identical draws and greedy sets."""
