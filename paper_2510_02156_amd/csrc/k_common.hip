@@ -156,7 +156,9 @@ __device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint3
     *omn = c;
 }
 
-// Radix select over keys[0..N) in LDS.  The 32-bit view (key >> shift) of the
+// Radix select over the N keys that the workgroup holds in registers: element
+// i = threadIdx.x + u * SEL_T is kv[u] of its thread (u < PER; every
+// histogram pass reads registers, not LDS).  The 32-bit view (key >> shift) of the
 // largest and the smallest key (vmax, vmin, from block_minmax_u32) share
 // their leading bits with every key, so the search starts at the highest bit
 // where the two differ and spends no pass on a common prefix.  Digits of up to
@@ -164,8 +166,10 @@ __device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint3
 // and the number `need` of elements whose masked key equals T that complete
 // the top K (elements with a larger masked key are all in).  Stops as soon as
 // the boundary bucket holds exactly `need` elements.
-__device__ void radix_select(const uint64_t *keys, int N, int K, int shift, uint32_t vmax,
-                             uint32_t vmin, uint64_t *T_out, uint64_t *mask_out, int *need_out) {
+template <int PER>
+__device__ __forceinline__ void radix_select(const uint64_t (&kv)[PER], int N, int K, int shift,
+                                             uint32_t vmax, uint32_t vmin, uint64_t *T_out,
+                                             uint64_t *mask_out, int *need_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int s_need, s_stop;
@@ -188,12 +192,14 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int shift, uint
     for (int hi = top; hi >= 0; hi -= 8) {
         const int lo = hi >= 7 ? hi - 7 : 0;
         const uint64_t dmask = (1ull << (hi - lo + 1)) - 1ull;
-        for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[b] = 0;
+        for (int b = threadIdx.x; b < 256; b += SEL_T) hist[b] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix, mask = s_mask;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            const uint64_t kk = keys[i];
-            if (((kk ^ prefix) & mask) == 0) atomicAdd(&hist[(kk >> lo) & dmask], 1u);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * SEL_T;
+            if (i < N && ((kv[u] ^ prefix) & mask) == 0)
+                atomicAdd(&hist[(kv[u] >> lo) & dmask], 1u);
         }
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -236,34 +242,28 @@ __device__ void radix_select(const uint64_t *keys, int N, int K, int shift, uint
 
 // Emit, in ascending index order, every element whose masked key exceeds T
 // and the first `need` elements whose masked key equals T (K in total).
-// Element i is taken by thread i % NT in round i / NT, so index order is
-// (round, wave, lane): ranks within a wave come from ballots, and the counts
-// of earlier (round, wave) pairs from one scan over their totals.  keys/ids
-// in LDS (ids == NULL: the position); outputs get base added.  Rounds past
-// the last element (N <= ROUNDS * NT) are skipped by a uniform branch.
-template <int NT, int ROUNDS>
-__device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, int K, uint64_t T,
-                             uint64_t mask, int need, uint64_t *okey, int32_t *oidx,
-                             int32_t base) {
+// Element i = threadIdx.x + u * NT is kv[u] (and iv[u] with IDS, else its
+// position i) of its thread, so index order is (round, wave, lane): ranks
+// within a wave come from ballots, and the counts of earlier (round, wave)
+// pairs from one scan over their totals.  Outputs get base added to the index.
+template <int NT, int ROUNDS, bool IDS>
+__device__ __forceinline__ void compact_topk(const uint64_t (&kv)[ROUNDS],
+                                             const int32_t (&iv)[ROUNDS], int N, int K,
+                                             uint64_t T, uint64_t mask, int need, uint64_t *okey,
+                                             int32_t *oidx, int32_t base) {
     constexpr int NW = NT / 64, NS = ROUNDS * NW;
     static_assert(NS <= 128, "one scan lane holds two (round, wave) totals");
     // totals per (round, wave): greater-than count << 16 | equal count
     // (each at most N <= 8192, so neither half carries into the other)
     __shared__ uint32_t wcnt[NS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nr = (N + NT - 1) / NT;   // rounds holding elements
     // per round: rank among the wave's "greater" lanes (bits 0..7), among its
     // "equal" lanes (bits 8..15), and the two flags (bits 16, 17)
     uint32_t rk[ROUNDS];
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
-        rk[u] = 0u;
-        if (u >= nr) {
-            if (lane == 0) wcnt[u * NW + w] = 0u;
-            continue;
-        }
         const int i = threadIdx.x + u * NT;
-        const uint64_t mk = (i < N) ? (keys[i] & mask) : 0;
+        const uint64_t mk = kv[u] & mask;
         const bool gt = (i < N) && mk > T, eq = (i < N) && mk == T;
         const unsigned long long bg = __ballot(gt), be = __ballot(eq);
         const uint32_t rg = __builtin_amdgcn_mbcnt_hi((uint32_t)(bg >> 32),
@@ -287,48 +287,48 @@ __device__ void compact_topk(const uint64_t *keys, const int32_t *ids, int N, in
         if (a + 1 < NS) wcnt[a + 1] = ex + c0;
     }
     __syncthreads();
+    uint32_t bf[ROUNDS];
+#pragma unroll
+    for (int u = 0; u < ROUNDS; ++u) bf[u] = wcnt[u * NW + w];
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
-        if (u < nr) {
-            const int i = threadIdx.x + u * NT;
-            const uint32_t before = wcnt[u * NW + w];
-            const uint32_t g = (before >> 16) + (rk[u] & 0xffu);
-            const uint32_t q = (before & 0xffffu) + ((rk[u] >> 8) & 0xffu);
-            int pos = -1;
-            if (rk[u] & 0x10000u) pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
-            else if ((rk[u] & 0x20000u) && q < (uint32_t)need) pos = (int)(g + q);
-            if (pos >= 0 && pos < K) {
-                okey[pos] = keys[i];
-                oidx[pos] = (ids ? ids[i] : i) + base;
-            }
+        const int i = threadIdx.x + u * NT;
+        const uint32_t g = (bf[u] >> 16) + (rk[u] & 0xffu);
+        const uint32_t q = (bf[u] & 0xffffu) + ((rk[u] >> 8) & 0xffu);
+        int pos = -1;
+        if (rk[u] & 0x10000u) pos = (int)(g + (q < (uint32_t)need ? q : (uint32_t)need));
+        else if ((rk[u] & 0x20000u) && q < (uint32_t)need) pos = (int)(g + q);
+        if (pos >= 0 && pos < K) {
+            okey[pos] = kv[u];
+            oidx[pos] = (IDS ? iv[u] : i) + base;
         }
     }
     __syncthreads();
 }
 
-// Merge of nlists candidate lists (each K long, ascending rows) from ckey /
-// cidx into the K largest, in LDS keys / ids (N = nlists * K <= SEL_MERGE).
-template <typename V>
-__device__ void merge_lists(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
-                            int N, int K, uint64_t *keys, int32_t *ids, uint64_t *okey,
-                            int32_t *oidx) {
-    constexpr int PER = SEL_MERGE / SEL_T;
+// Merge of candidate lists (each K long, ascending rows) from ckey / cidx
+// into the K largest, written to okey / oidx (N = nlists * K <= PER * SEL_T
+// candidates, held in registers).
+template <typename V, int PER>
+__device__ __forceinline__ void merge_lists_r(const uint64_t *__restrict__ ckey,
+                                              const int32_t *__restrict__ cidx, int N, int K,
+                                              uint64_t *okey, int32_t *oidx) {
     constexpr int SH = sizeof(V) == 8 ? 32 : 0;
     uint64_t kv[PER];
     int32_t iv[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int i = threadIdx.x + u * SEL_T;
-        kv[u] = (i < N) ? ckey[i] : 0;
-        iv[u] = (i < N) ? cidx[i] : 0;
+        const uint64_t tk = ckey[i < N ? i : 0];
+        const int32_t ti = cidx[i < N ? i : 0];
+        kv[u] = (i < N) ? tk : 0;
+        iv[u] = (i < N) ? ti : 0;
     }
     uint32_t vmx = 0u, vmn = 0xffffffffu;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int i = threadIdx.x + u * SEL_T;
         if (i < N) {
-            keys[i] = kv[u];
-            ids[i] = iv[u];
             const uint32_t v = (uint32_t)(kv[u] >> SH);
             vmx = v > vmx ? v : vmx;
             vmn = v < vmn ? v : vmn;
@@ -338,33 +338,52 @@ __device__ void merge_lists(const uint64_t *__restrict__ ckey, const int32_t *__
     block_minmax_u32(vmx, vmn, &vmax, &vmin);
     uint64_t T, mask;
     int need;
-    radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
-    compact_topk<SEL_T, SEL_MERGE / SEL_T>(keys, ids, N, K, T, mask, need, okey, oidx, 0);
+    radix_select<PER>(kv, N, K, SH, vmax, vmin, &T, &mask, &need);
+    compact_topk<SEL_T, PER, true>(kv, iv, N, K, T, mask, need, okey, oidx, 0);
+}
+
+template <typename V>
+__device__ __forceinline__ void merge_lists(const uint64_t *__restrict__ ckey,
+                                            const int32_t *__restrict__ cidx, int N, int K,
+                                            uint64_t *okey, int32_t *oidx) {
+    if (N <= 4 * SEL_T) merge_lists_r<V, 4>(ckey, cidx, N, K, okey, oidx);
+    else merge_lists_r<V, SEL_MERGE / SEL_T>(ckey, cidx, N, K, okey, oidx);
 }
 
 // The end of an iteration's selection (one workgroup): the last candidate
 // merge (if do_topk and there is more than one list), the RRN from the chunk norms (strided lane sums, then a
 // fixed butterfly), the stop test, the greedy set I (or the replayed one)
-// with r_I, and the records.
-// keys / ids / s_cn: LDS of SEL_MERGE, SEL_MERGE and SEL_MERGE / 4 entries.
+// with r_I, and the records.  The chunk norms are loaded together with the
+// candidates.  ids / s_cn: LDS of MAXK and SEL_NCN entries.
+constexpr int SEL_NCN = SEL_MERGE / 4;   // chunk norms held in LDS (the rest read again)
 template <typename V>
-__device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
+__device__ __forceinline__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *__restrict__ cidx,
                              int nlists, int K, const double *__restrict__ cn, int ncn,
                              const V *__restrict__ r, Ctrl *__restrict__ ctrl, int stop_test,
                              int do_topk, int64_t it, double *rec_rrn, int32_t *rec_I,
                              const int32_t *replay_I, int32_t *I_out, double *rI_out,
-                             uint64_t *keys, int32_t *ids, double *s_cn) {
+                             int32_t *ids, double *s_cn) {
     __shared__ int s_stop;
     __shared__ uint64_t fk[MAXK];
     __shared__ int32_t fi[MAXK];
-    constexpr int NCN = SEL_MERGE / 4;
-    for (int c = threadIdx.x; c < ncn && c < NCN; c += blockDim.x) s_cn[c] = cn[c];
+    constexpr int NCN = SEL_NCN, CPT = SEL_NCN / SEL_T;
+    double cnv[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int c = threadIdx.x + u * SEL_T;
+        cnv[u] = cn[c < ncn ? c : 0];
+    }
     if (do_topk && nlists > 1) {
-        merge_lists<V>(ckey, cidx, nlists * K, K, keys, ids, fk, fi);
-        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = fi[p];
+        merge_lists<V>(ckey, cidx, nlists * K, K, fk, fi);
+        for (int p = threadIdx.x; p < K; p += SEL_T) ids[p] = fi[p];
     } else if (do_topk) {
         // one chunk: its list (ascending rows) is the top K
-        for (int p = threadIdx.x; p < K; p += blockDim.x) ids[p] = cidx[p];
+        for (int p = threadIdx.x; p < K; p += SEL_T) ids[p] = cidx[p];
+    }
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int c = threadIdx.x + u * SEL_T;
+        if (c < ncn) s_cn[c] = cnv[u];
     }
     __syncthreads();
     // ||r||^2 from the chunk norms: lane l of wave 0 sums chunks l, l + 64,
@@ -397,7 +416,7 @@ __device__ void select_final(const uint64_t *__restrict__ ckey, const int32_t *_
     }
     __syncthreads();
     if (s_stop || !I_out) return;
-    for (int p = threadIdx.x; p < K; p += blockDim.x) {
+    for (int p = threadIdx.x; p < K; p += SEL_T) {
         const int32_t row = replay_I ? replay_I[it * K + p] : ids[p];
         I_out[p] = row;
         rI_out[p] = (double)r[row];
@@ -416,17 +435,16 @@ __global__ __launch_bounds__(SEL_T) void k_select_merge(
     Ctrl *__restrict__ ctrl, int stop_test, int do_topk, int64_t it, double *rec_rrn,
     int32_t *rec_I, const int32_t *replay_I, int32_t *I_out, double *rI_out) {
     if (ctrl->done) return;
-    __shared__ uint64_t keys[SEL_MERGE];
-    __shared__ int32_t ids[SEL_MERGE];
-    __shared__ double s_cn[SEL_MERGE / 4];
+    __shared__ int32_t ids[MAXK];
+    __shared__ double s_cn[SEL_NCN];
     if (final_level) {
         select_final<V>(ckey, cidx, nlists, K, cn, ncn, r, ctrl, stop_test, do_topk, it, rec_rrn,
-                        rec_I, replay_I, I_out, rI_out, keys, ids, s_cn);
+                        rec_I, replay_I, I_out, rI_out, ids, s_cn);
         return;
     }
     const int l0 = blockIdx.x * lists_per_group;
     const int l1 = (l0 + lists_per_group < nlists) ? l0 + lists_per_group : nlists;
-    merge_lists<V>(ckey + (int64_t)l0 * K, cidx + (int64_t)l0 * K, (l1 - l0) * K, K, keys, ids,
+    merge_lists<V>(ckey + (int64_t)l0 * K, cidx + (int64_t)l0 * K, (l1 - l0) * K, K,
                    okey + (int64_t)blockIdx.x * K, oidx + (int64_t)blockIdx.x * K);
 }
 
@@ -448,10 +466,11 @@ struct SelFinal {
     double *rI_out;
 };
 
-// LDS of the selection kernels: a chunk's keys, values and block norms, then
-// (fused form, last workgroup) the merge's keys, indices and chunk norms.
-constexpr int SEL_LDS = (SEL_MERGE * 8 + SEL_MERGE * 4 + (SEL_MERGE / 4) * 8) / 8;
-static_assert(2 * SEL_CHUNK + SEL_BPC <= SEL_LDS, "a chunk's keys, values and block norms fit");
+// LDS of the selection kernels (8-byte words): a chunk's values and block
+// norms, then (fused form, last workgroup) the greedy rows and chunk norms.
+constexpr int SEL_LDS = (SEL_CHUNK + SEL_BPC > MAXK / 2 + SEL_NCN) ? SEL_CHUNK + SEL_BPC
+                                                                   : MAXK / 2 + SEL_NCN;
+static_assert(MAXK % 2 == 0, "the chunk norms follow the greedy rows 8-byte aligned");
 
 // Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
 // (Algorithm 1, the full residual), per-block ||r_t||^2, the chunk's ||r||^2,
@@ -467,9 +486,8 @@ __device__ __forceinline__ void select_chunk(
     int do_topk, const Ctrl *__restrict__ ctrl, const SelFinal<V> &fin, int nchunks) {
     __shared__ uint64_t sel_lds[SEL_LDS];
     __shared__ int s_last;
-    uint64_t *keys = sel_lds;                                   // SEL_CHUNK
-    double *vals = reinterpret_cast<double *>(sel_lds + SEL_CHUNK);   // SEL_CHUNK
-    double *s_bn = reinterpret_cast<double *>(sel_lds + 2 * SEL_CHUNK); // SEL_BPC
+    double *vals = reinterpret_cast<double *>(sel_lds);               // SEL_CHUNK
+    double *s_bn = reinterpret_cast<double *>(sel_lds + SEL_CHUNK);   // SEL_BPC
     const int64_t t0 = (int64_t)blockIdx.x * bpc;
     const int64_t t1 = (t0 + bpc < k) ? t0 + bpc : k;
     const int64_t r0 = blk_start(t0, q, rem), r1 = blk_start(t1, q, rem);
@@ -482,7 +500,8 @@ __device__ __forceinline__ void select_chunk(
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int i = threadIdx.x + u * SEL_T;
-        bv[u] = (i < N) ? b[r0 + i] : (V)0;
+        const V t = b[r0 + (i < N ? i : 0)];
+        bv[u] = (i < N) ? t : (V)0;
         av[u] = 0.0;
     }
     if (axp) {
@@ -491,7 +510,8 @@ __device__ __forceinline__ void select_chunk(
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const int i = threadIdx.x + u * SEL_T;
-                t[u] = (i < N) ? axp[(int64_t)sg * m + r0 + i] : 0.0;
+                const double tv = axp[(int64_t)sg * m + r0 + (i < N ? i : 0)];
+                t[u] = (i < N) ? tv : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < PER; ++u) av[u] += t[u];
@@ -499,16 +519,18 @@ __device__ __forceinline__ void select_chunk(
     }
     if (ctrl && ctrl->done) return;
     uint32_t vmx = 0u, vmn = 0xffffffffu;
+    uint64_t kr[PER];   // the keys, kept in registers for the selection
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int i = threadIdx.x + u * SEL_T;
+        kr[u] = 0;
         if (i < N) {
             const V s = axp ? (V)((double)bv[u] - av[u]) : bv[u];
             const uint64_t kk = key_of(s);
             const uint32_t v = (uint32_t)(kk >> SH);
             r[r0 + i] = s;
             vals[i] = (double)s;
-            keys[i] = kk;
+            kr[u] = kk;
             vmx = v > vmx ? v : vmx;
             vmn = v < vmn ? v : vmn;
         }
@@ -524,6 +546,7 @@ __device__ __forceinline__ void select_chunk(
             const int s0 = (int)(blk_start(t, q, rem) - r0);
             const int bt = blk_rows(t, q, rem);
             double s = 0.0;
+#pragma unroll 4
             for (int i = j; i < bt; i += 8) s = __builtin_fma(vals[s0 + i], vals[s0 + i], s);
             s += __shfl_xor(s, 4, 64);
             s += __shfl_xor(s, 2, 64);
@@ -548,10 +571,11 @@ __device__ __forceinline__ void select_chunk(
     if (do_topk) {
         uint64_t T, mask;
         int need;
-        radix_select(keys, N, K, SH, vmax, vmin, &T, &mask, &need);
-        compact_topk<SEL_T, SEL_CHUNK / SEL_T>(keys, nullptr, N, K, T, mask, need,
-                                               ckey + (int64_t)blockIdx.x * K,
-                                               cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
+        const int32_t none[PER] = {};   // (positions stand for the indices)
+        radix_select<PER>(kr, N, K, SH, vmax, vmin, &T, &mask, &need);
+        compact_topk<SEL_T, PER, false>(kr, none, N, K, T, mask, need,
+                                        ckey + (int64_t)blockIdx.x * K,
+                                        cidx + (int64_t)blockIdx.x * K, (int32_t)r0);
     }
     if (!fin.counter) return;
     // count this workgroup done; the acquire-release device-scope atomic
@@ -567,8 +591,8 @@ __device__ __forceinline__ void select_chunk(
     if (threadIdx.x == 0) *fin.counter = 0u;   // ready for the next launch
     select_final<V>(ckey, cidx, fin.nlists, K, fin.cn, fin.ncn, r, fin.ctrl, fin.stop_test,
                     do_topk, fin.it, fin.rec_rrn, fin.rec_I, fin.replay_I, fin.I_out, fin.rI_out,
-                    sel_lds, reinterpret_cast<int32_t *>(sel_lds + SEL_MERGE),
-                    reinterpret_cast<double *>(sel_lds + SEL_MERGE + SEL_MERGE / 2));
+                    reinterpret_cast<int32_t *>(sel_lds),
+                    reinterpret_cast<double *>(sel_lds + MAXK / 2));
 }
 
 template <typename V>
