@@ -156,8 +156,23 @@ __device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint3
     *omn = c;
 }
 
-// Radix select over the N keys that the workgroup holds in registers: element
-// i = threadIdx.x + u * SEL_T is kv[u] of its thread (u < PER; every
+// Inclusive prefix sum of a 32-bit count over the 64 lanes of a wave, lane 0
+// first: sums within each row of 16 lanes by row_shr 1, 2, 4, 8 (lanes that
+// would read from outside their row add 0), then rows 1 and 3 add the last
+// lane of rows 0 and 2 (row_bcast:15) and rows 2 and 3 the last lane of row 1
+// (row_bcast:31).  Integer sums, so the order of the additions is immaterial.
+__device__ __forceinline__ uint32_t wave_prefix_sum_u32(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
+// Radix select over the N >= K keys that the workgroup holds in registers:
+// element i = threadIdx.x + u * SEL_T is kv[u] of its thread (u < PER; every
 // histogram pass reads registers, not LDS).  The 32-bit view (key >> shift) of the
 // largest and the smallest key (vmax, vmin, from block_minmax_u32) share
 // their leading bits with every key, so the search starts at the highest bit
@@ -165,14 +180,17 @@ __device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint3
 // 8 bits follow, most significant first: finds a masked threshold (T, mask)
 // and the number `need` of elements whose masked key equals T that complete
 // the top K (elements with a larger masked key are all in).  Stops as soon as
-// the boundary bucket holds exactly `need` elements.
+// the boundary bucket holds exactly `need` elements.  One barrier per pass:
+// every wave reads the whole histogram and finds the boundary bin itself (the
+// same result in every wave), and the pass also clears the histogram of the
+// pass after next of three in rotation (the one every wave finished reading
+// before the previous pass's barrier).
 template <int PER>
 __device__ __forceinline__ void radix_select(const uint64_t (&kv)[PER], int N, int K, int shift,
                                              uint32_t vmax, uint32_t vmin, uint64_t *T_out,
                                              uint64_t *mask_out, int *need_out) {
-    __shared__ uint32_t hist[256];
-    __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int s_need, s_stop;
+    static_assert(SEL_T >= 256, "one thread per bin clears a histogram");
+    __shared__ uint32_t hist[3][256];
     const uint32_t dv = vmax ^ vmin;
     if (dv == 0 && shift == 0) {  // all keys equal: the first K by index
         *T_out = (uint64_t)vmax;
@@ -182,62 +200,56 @@ __device__ __forceinline__ void radix_select(const uint64_t (&kv)[PER], int N, i
     }
     // highest differing bit (bit shift - 1 if the views agree)
     const int top = dv ? shift + 31 - __clz((int)dv) : shift - 1;
-    if (threadIdx.x == 0) {
-        const uint64_t pm = ~((2ull << top) - 1ull);
-        s_prefix = ((uint64_t)vmax << shift) & pm;
-        s_mask = pm;
-        s_need = K;
-        s_stop = 0;
-    }
+    const uint64_t pm = ~((2ull << top) - 1ull);
+    uint64_t prefix = ((uint64_t)vmax << shift) & pm, mask = pm;
+    int need = K;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 256) hist[0][threadIdx.x] = 0u;
+    __syncthreads();
+    int p = 0;
     for (int hi = top; hi >= 0; hi -= 8) {
         const int lo = hi >= 7 ? hi - 7 : 0;
         const uint64_t dmask = (1ull << (hi - lo + 1)) - 1ull;
-        for (int b = threadIdx.x; b < 256; b += SEL_T) hist[b] = 0;
-        __syncthreads();
-        const uint64_t prefix = s_prefix, mask = s_mask;
+        uint32_t *H = hist[p];
+        const int pn = (p == 2) ? 0 : p + 1;
+        if (threadIdx.x < 256) hist[pn][threadIdx.x] = 0u;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int i = threadIdx.x + u * SEL_T;
             if (i < N && ((kv[u] ^ prefix) & mask) == 0)
-                atomicAdd(&hist[(kv[u] >> lo) & dmask], 1u);
+                atomicAdd(&H[(kv[u] >> lo) & dmask], 1u);
         }
         __syncthreads();
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            uint32_t h[4];
-            uint32_t ls = 0;
+        p = pn;
+        // lane l holds bins 4 (63 - l) .. 4 (63 - l) + 3, so the prefix sum
+        // over lanes counts the elements in bins >= 4 (63 - l)
+        uint32_t h[4];
+        uint32_t ls = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) { h[u] = hist[4 * lane + u]; ls += h[u]; }
-            // inclusive suffix sums over lanes (higher bins first)
-            uint32_t suf = ls;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t t = __shfl_down(suf, off, 64);
-                if (lane + off < 64) suf += t;
-            }
-            const int need = s_need;
-            const unsigned long long bal = __ballot(suf >= (uint32_t)need);
-            const int topl = 63 - __clzll(bal);   // the highest lane reaching `need`
-            if (lane == topl) {
-                uint32_t above = suf - ls;
-                int bin = 4 * lane;
-                uint32_t inbin = h[0];
-                for (int u = 3; u >= 0; --u) {
-                    if (above + h[u] >= (uint32_t)need) { bin = 4 * lane + u; inbin = h[u]; break; }
-                    above += h[u];
-                }
-                s_need = need - (int)above;
-                s_prefix = prefix | ((uint64_t)bin << lo);
-                s_mask = mask | (dmask << lo);
-                s_stop = (inbin == (uint32_t)(need - (int)above)) ? 1 : 0;
-            }
+        for (int u = 0; u < 4; ++u) { h[u] = H[4 * (63 - lane) + u]; ls += h[u]; }
+        const uint32_t pre = wave_prefix_sum_u32(ls);
+        const unsigned long long bal = __ballot(pre >= (uint32_t)need);
+        if (bal == 0ull) continue;   // (not reached: N >= K)
+        const int fl = __ffsll((long long)bal) - 1;   // the lowest lane reaching `need`
+        uint32_t above = (uint32_t)__builtin_amdgcn_readlane((int)pre, fl) -
+                         (uint32_t)__builtin_amdgcn_readlane((int)ls, fl);
+        uint32_t hf[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hf[u] = (uint32_t)__builtin_amdgcn_readlane((int)h[u], fl);
+        int bin = 4 * (63 - fl);
+        uint32_t inbin = hf[0];
+        for (int u = 3; u >= 0; --u) {
+            if (above + hf[u] >= (uint32_t)need) { bin = 4 * (63 - fl) + u; inbin = hf[u]; break; }
+            above += hf[u];
         }
-        __syncthreads();
-        if (s_stop) break;
+        need -= (int)above;
+        prefix |= (uint64_t)bin << lo;
+        mask |= dmask << lo;
+        if (inbin == (uint32_t)need) break;
     }
-    *T_out = s_prefix;
-    *mask_out = s_mask;
-    *need_out = s_need;
-    __syncthreads();
+    *T_out = prefix;
+    *mask_out = mask;
+    *need_out = need;
 }
 
 // Emit, in ascending index order, every element whose masked key exceeds T
