@@ -132,30 +132,6 @@ constexpr int SEL_CHUNK = 4096;     // rows per selection chunk (upper bound)
 constexpr int SEL_MERGE = 8192;     // candidates per merge workgroup
 constexpr int SEL_BPC = 256;        // blocks per selection chunk (upper bound)
 
-// Largest and smallest of a per-thread 32-bit value over the workgroup: a
-// butterfly within each wave, then the per-wave results through LDS.  Every
-// thread receives both.  Contains one __syncthreads.
-__device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint32_t *omx,
-                                                 uint32_t *omn) {
-    __shared__ uint32_t wmx[16], wmn[16];
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t a = (uint32_t)__shfl_xor((int)mx, off, 64);
-        const uint32_t c = (uint32_t)__shfl_xor((int)mn, off, 64);
-        mx = a > mx ? a : mx;
-        mn = c < mn ? c : mn;
-    }
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0) { wmx[w] = mx; wmn[w] = mn; }
-    __syncthreads();
-    uint32_t a = wmx[0], c = wmn[0];
-    for (int i = 1; i < nw; ++i) {
-        a = wmx[i] > a ? wmx[i] : a;
-        c = wmn[i] < c ? wmn[i] : c;
-    }
-    *omx = a;
-    *omn = c;
-}
-
 // Inclusive prefix sum of a 32-bit count over the 64 lanes of a wave, lane 0
 // first: sums within each row of 16 lanes by row_shr 1, 2, 4, 8 (lanes that
 // would read from outside their row add 0), then rows 1 and 3 add the last
@@ -169,6 +145,41 @@ __device__ __forceinline__ uint32_t wave_prefix_sum_u32(uint32_t x) {
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
     return x;
+}
+
+// Largest 32-bit value over the 64 lanes of a wave, in every lane: the
+// prefix maximum by the same DPP steps as wave_prefix_sum_u32 (0 is the
+// identity), read from the last lane.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    uint32_t t;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false); x = t > x ? t : x;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false); x = t > x ? t : x;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false); x = t > x ? t : x;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false); x = t > x ? t : x;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false); x = t > x ? t : x;
+    t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false); x = t > x ? t : x;
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Largest and smallest of a per-thread 32-bit value over the workgroup: DPP
+// steps within each wave (the smallest as the complement of the largest
+// complement), then the per-wave results through LDS.  Every thread receives
+// both.  Contains one __syncthreads.
+__device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint32_t *omx,
+                                                 uint32_t *omn) {
+    __shared__ uint32_t wmx[16], wmn[16];
+    mx = wave_max_u32(mx);
+    mn = ~wave_max_u32(~mn);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) { wmx[w] = mx; wmn[w] = mn; }
+    __syncthreads();
+    uint32_t a = wmx[0], c = wmn[0];
+    for (int i = 1; i < nw; ++i) {
+        a = wmx[i] > a ? wmx[i] : a;
+        c = wmn[i] < c ? wmn[i] : c;
+    }
+    *omx = a;
+    *omn = c;
 }
 
 // Radix select over the N >= K keys that the workgroup holds in registers:
@@ -286,22 +297,20 @@ __device__ __forceinline__ void compact_topk(const uint64_t (&kv)[ROUNDS],
         if (lane == 0) wcnt[u * NW + w] = ((uint32_t)__popcll(bg) << 16) | (uint32_t)__popcll(be);
     }
     __syncthreads();
-    if (threadIdx.x < 64) {   // exclusive scan of the totals in (round, wave) order
-        const int a = 2 * lane;
-        const uint32_t c0 = (a < NS) ? wcnt[a] : 0u, c1 = (a + 1 < NS) ? wcnt[a + 1] : 0u;
-        uint32_t inc = c0 + c1;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t t = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += t;
-        }
-        const uint32_t ex = inc - c0 - c1;
-        if (a < NS) wcnt[a] = ex;
-        if (a + 1 < NS) wcnt[a + 1] = ex + c0;
-    }
-    __syncthreads();
+    // every wave scans the totals itself (exclusive, in (round, wave) order;
+    // lane a holds entries 2a and 2a + 1) and takes its own entries
+    const int a = 2 * lane;
+    const uint32_t c0 = (a < NS) ? wcnt[a] : 0u, c1 = (a + 1 < NS) ? wcnt[a + 1] : 0u;
+    const uint32_t ex = wave_prefix_sum_u32(c0 + c1) - c0 - c1;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     uint32_t bf[ROUNDS];
 #pragma unroll
-    for (int u = 0; u < ROUNDS; ++u) bf[u] = wcnt[u * NW + w];
+    for (int u = 0; u < ROUNDS; ++u) {
+        const int e = u * NW + wu;
+        const uint32_t el = (uint32_t)__builtin_amdgcn_readlane((int)ex, e >> 1);
+        const uint32_t cl = (uint32_t)__builtin_amdgcn_readlane((int)c0, e >> 1);
+        bf[u] = el + ((e & 1) ? cl : 0u);
+    }
 #pragma unroll
     for (int u = 0; u < ROUNDS; ++u) {
         const int i = threadIdx.x + u * NT;
