@@ -103,7 +103,10 @@ __host__ __device__ inline int gram_chain_tiles(int K, int bmax) {
 
 template <typename T, bool AL>
 __global__ __launch_bounds__(64 * GC_W) void k_gram_chain(GramChainP p) {
-    if (p.ctrl->done) return;
+    // the stop flag is read together with the row indices: one memory
+    // latency before the row loads instead of two
+    const int stop =
+        __hip_atomic_load(&p.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     constexpr int E = (sizeof(T) == 8) ? 4 : Tr<T>::VW;
     const T *__restrict__ A = (const T *)p.A;
     const int K = p.K;
@@ -116,21 +119,29 @@ __global__ __launch_bounds__(64 * GC_W) void k_gram_chain(GramChainP p) {
     if (job < ntg) {                 // greedy Gram, lower tiles
         kind = 0;
         tile_of(job, nt, &bi, &bj);
-        ra = (bi * 16 + li < K) ? (int64_t)p.I[bi * 16 + li] : -1;
-        rb = (bj * 16 + li < K) ? (int64_t)p.I[bj * 16 + li] : -1;
-    } else if (job < ntg + nc) {     // C: block l of S' against I
+    } else {                         // C: block l of S' against I
         kind = 1;
         const int c = job - ntg;
         l = c / (nb * nt);
         const int rest = c - l * nb * nt;
         bi = rest / nt;
         bj = rest - bi * nt;
+    }
+    // the greedy rows of this lane, read with clamped indices (no branch
+    // around the loads) before the sampled block's start
+    const int ia = bi * 16 + li, ib = bj * 16 + li;
+    const int32_t Ia = p.I[ia < K ? ia : K - 1];
+    const int32_t Ib = p.I[ib < K ? ib : K - 1];
+    rb = (ib < K) ? (int64_t)Ib : -1;
+    if (kind == 0) {
+        ra = (ia < K) ? (int64_t)Ia : -1;
+    } else {
         const int64_t t = p.tau[p.ti + l];
         ca = blk_rows(t, p.q, p.rem);
         if (bi * 16 >= ca) return;   // uniform: a tile past the block
-        ra = (bi * 16 + li < ca) ? blk_start(t, p.q, p.rem) + bi * 16 + li : -1;
-        rb = (bj * 16 + li < K) ? (int64_t)p.I[bj * 16 + li] : -1;
+        ra = (ia < ca) ? blk_start(t, p.q, p.rem) + ia : -1;
     }
+    if (stop) return;
     const int64_t c0 = (int64_t)ch * p.wc;
     const int64_t c1 = (c0 + p.wc < p.n) ? c0 + p.wc : p.n;
     const int64_t stepc = 4 * E;
