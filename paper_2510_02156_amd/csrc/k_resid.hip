@@ -47,8 +47,38 @@ __device__ __forceinline__ uvec4 clear_outside(uvec4 w, int64_t c, int64_t n) {
     return w;
 }
 
+// x[c .. c + VW) into registers, zero outside [0, n): 16-byte loads when
+// `vec` (x 16-byte aligned and every lane's slice inside [0, n): a
+// wave-uniform condition, so that no lane's element loads write registers
+// another lane's 16-byte loads are still filling), element loads otherwise.
+// c is a multiple of 16 bytes.  Every wave reads its slice of x once, so
+// these loads are a sizeable share of the pass's load instructions.
+template <typename V, int VW>
+__device__ __forceinline__ void x_slice(const V *__restrict__ x, int64_t c, int64_t n, bool vec,
+                                        V (&out)[VW]) {
+    constexpr int PQ = 16 / sizeof(V);   // elements per 16-byte load
+    static_assert(VW % PQ == 0, "whole 16-byte loads per slice");
+    if (vec) {
+#pragma unroll
+        for (int qd = 0; qd < VW / PQ; ++qd) {
+            const uvec4 t = *reinterpret_cast<const uvec4 *>(x + c + qd * PQ);
+            __builtin_memcpy(&out[qd * PQ], &t, 16);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) out[e] = (c + e >= 0 && c + e < n) ? x[c + e] : (V)0;
+    }
+}
+
+// Waves per SIMD at most: FP32 rows of full segments stream fastest with
+// three (measured: 114.5 us against 118.9 us with four on the tall 100000 x
+// 2000 matrix); the other forms are bounded by their registers.
+template <typename T, int SW>
+constexpr int resid_waves() { return (sizeof(T) == 4 && SW == SEG) ? 3 : 8; }
+
 template <typename T, typename V, bool AL, int ROWS, int SW, bool SH = false>
-__global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, int64_t ld,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, resid_waves<T, SW>())))
+void k_resid_dense(const T *__restrict__ A, int64_t ld,
                                                      int64_t m, int64_t n,
                                                      const V *__restrict__ x,
                                                      double *__restrict__ axp,
@@ -65,21 +95,21 @@ __global__ __launch_bounds__(256) void k_resid_dense(const T *__restrict__ A, in
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t seg = blockIdx.y;
     const int64_t c0 = seg * SEG;
+    // slice s of the wave covers columns c0 + s * 64 * VW + [0, 64 * VW)
+    const bool xal = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
     V xr[NVL][VW];
 #pragma unroll
     for (int s = 0; s < NVL; ++s) {
-        const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW;
-#pragma unroll
-        for (int e = 0; e < VW; ++e) xr[s][e] = (col + e < n) ? x[col + e] : (V)0;
+        const int64_t cw = c0 + (int64_t)s * WAVE * VW;
+        x_slice<V, VW>(x, cw + (int64_t)lane * VW, n, xal && cw + WAVE * VW <= n, xr[s]);
     }
     V xs[SH ? NVL : 1][VW];   // x moved back by half a vector (SH)
     if constexpr (SH) {
 #pragma unroll
         for (int s = 0; s < NVL; ++s) {
-            const int64_t col = c0 + (int64_t)(s * WAVE + lane) * VW - VW / 2;
-#pragma unroll
-            for (int e = 0; e < VW; ++e)
-                xs[s][e] = (col + e >= 0 && col + e < n) ? x[col + e] : (V)0;
+            const int64_t cw = c0 + (int64_t)s * WAVE * VW - VW / 2;
+            x_slice<V, VW>(x, cw + (int64_t)lane * VW, n, xal && cw >= 0 && cw + WAVE * VW <= n,
+                           xs[s]);
         }
     }
     const int64_t last = (m - 1) * ld + n;   // one past the matrix's last element
