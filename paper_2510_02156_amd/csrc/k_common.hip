@@ -493,13 +493,77 @@ constexpr int SEL_LDS = (SEL_CHUNK + SEL_BPC > MAXK / 2 + SEL_NCN) ? SEL_CHUNK +
                                                                    : MAXK / 2 + SEL_NCN;
 static_assert(MAXK % 2 == 0, "the chunk norms follow the greedy rows 8-byte aligned");
 
+// The loads of a selection chunk: b and the sum over the nseg segments of the
+// partial products (in segment order) for element i = threadIdx.x + u * SEL_T
+// of the chunk's N rows.  FULL (every round holds rows): no branch around
+// any load.  Otherwise (a short chunk, nr < PER rounds, uniform) rounds past
+// the last row load nothing, since a workgroup summing many segments is
+// bound by the loads it issues, and the segments go in groups of GS whose
+// loads are all issued before any is added.
+template <typename V, int PER, bool FULL>
+__device__ __forceinline__ void chunk_loads(const V *__restrict__ b,
+                                            const double *__restrict__ axp, int nseg, int64_t m,
+                                            int64_t r0, int N, int nr, V (&bv)[PER],
+                                            double (&av)[PER]) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * SEL_T;
+        bv[u] = (V)0;
+        if (FULL || u < nr) {
+            const V t = b[r0 + (i < N ? i : 0)];
+            bv[u] = (i < N) ? t : (V)0;
+        }
+        av[u] = 0.0;
+    }
+    if (!axp) return;
+    int sg = 0;
+    if constexpr (!FULL) {
+        constexpr int GS = 4;
+        for (; sg + GS <= nseg; sg += GS) {
+            double t[GS][PER];
+#pragma unroll
+            for (int gq = 0; gq < GS; ++gq)
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int i = threadIdx.x + u * SEL_T;
+                    t[gq][u] = 0.0;
+                    if (u < nr) t[gq][u] = axp[(int64_t)(sg + gq) * m + r0 + (i < N ? i : 0)];
+                }
+#pragma unroll
+            for (int gq = 0; gq < GS; ++gq)
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int i = threadIdx.x + u * SEL_T;
+                    av[u] += (i < N) ? t[gq][u] : 0.0;
+                }
+        }
+    }
+    for (; sg < nseg; ++sg) {
+        double t[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * SEL_T;
+            t[u] = 0.0;
+            if (FULL || u < nr) {
+                const double tv = axp[(int64_t)sg * m + r0 + (i < N ? i : 0)];
+                t[u] = (i < N) ? tv : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) av[u] += t[u];
+    }
+}
+
 // Per selection chunk (a run of whole blocks): r_i = b_i - sum_seg axp[seg][i]
 // (Algorithm 1, the full residual), per-block ||r_t||^2, the chunk's ||r||^2,
 // and the chunk's local top-K candidates (keys, global row indices).  Fused
 // form (fin.counter set): every workgroup publishes its results (release
 // fence), counts itself done, and the last one (acquire fence) merges the
 // candidates and ends the selection, so no second kernel is launched.
-template <typename V>
+// SHORT: chunks with fewer rows than SEL_CHUNK take the short-chunk loads
+// (the plain selection kernel; the chain form's kernel, whose chunks are
+// full, keeps the one load path and its smaller register count).
+template <typename V, bool SHORT>
 __device__ __forceinline__ void select_chunk(
     const V *__restrict__ b, const double *__restrict__ axp, int nseg, int64_t m, int64_t q,
     int64_t rem, int64_t k, int64_t bpc, int K, V *__restrict__ r, double *__restrict__ bn,
@@ -516,28 +580,11 @@ __device__ __forceinline__ void select_chunk(
     constexpr int PER = SEL_CHUNK / SEL_T;
     constexpr int SH = sizeof(V) == 8 ? 32 : 0;   // the 32-bit view of a key
     // every load of the chunk in flight together with the stop flag's
+    const int nr = (N + SEL_T - 1) / SEL_T;   // rounds holding rows (uniform)
     V bv[PER];
     double av[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * SEL_T;
-        const V t = b[r0 + (i < N ? i : 0)];
-        bv[u] = (i < N) ? t : (V)0;
-        av[u] = 0.0;
-    }
-    if (axp) {
-        for (int sg = 0; sg < nseg; ++sg) {
-            double t[PER];
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int i = threadIdx.x + u * SEL_T;
-                const double tv = axp[(int64_t)sg * m + r0 + (i < N ? i : 0)];
-                t[u] = (i < N) ? tv : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < PER; ++u) av[u] += t[u];
-        }
-    }
+    if (!SHORT || nr == PER) chunk_loads<V, PER, true>(b, axp, nseg, m, r0, N, nr, bv, av);
+    else chunk_loads<V, PER, false>(b, axp, nseg, m, r0, N, nr, bv, av);
     if (ctrl && ctrl->done) return;
     uint32_t vmx = 0u, vmn = 0xffffffffu;
     uint64_t kr[PER];   // the keys, kept in registers for the selection
@@ -622,8 +669,8 @@ __global__ __launch_bounds__(SEL_T) void k_select_chunk(
     int64_t rem, int64_t k, int64_t bpc, int K, V *__restrict__ r, double *__restrict__ bn,
     double *__restrict__ cn, uint64_t *__restrict__ ckey, int32_t *__restrict__ cidx,
     int do_topk, const Ctrl *__restrict__ ctrl, SelFinal<V> fin) {
-    select_chunk<V>(b, axp, nseg, m, q, rem, k, bpc, K, r, bn, cn, ckey, cidx, do_topk, ctrl, fin,
-                    (int)gridDim.x);
+    select_chunk<V, true>(b, axp, nseg, m, q, rem, k, bpc, K, r, bn, cn, ckey, cidx, do_topk, ctrl,
+                          fin, (int)gridDim.x);
 }
 
 // The cross-Grams of the next iteration's blocks (xgram_tile with one wave
@@ -650,8 +697,8 @@ __global__ __launch_bounds__(SEL_T) void k_select_xg(
                                       xs.bmax, (int)blockIdx.x - nchunks, xs.out);
         return;
     }
-    select_chunk<V>(b, axp, nseg, m, q, rem, k, bpc, K, r, bn, cn, ckey, cidx, do_topk, ctrl, fin,
-                    nchunks);
+    select_chunk<V, false>(b, axp, nseg, m, q, rem, k, bpc, K, r, bn, cn, ckey, cidx, do_topk, ctrl,
+                           fin, nchunks);
 }
 static_assert(SEL_T == 512, "the selection's spare workgroups run the 8-wave cross-Gram tiles");
 

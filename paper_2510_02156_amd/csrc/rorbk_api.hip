@@ -69,6 +69,27 @@ void dfree(P *&p) {
 bool aligned16(const void *p, int64_t ld, size_t es) {
     return ((uintptr_t)p % 16 == 0) && ((ld * (int64_t)es) % 16 == 0);
 }
+// Blocks per selection chunk: whole blocks of at most 4096 rows (256 blocks).
+// With many column segments, chunks of at most 8192 partial products (one
+// workgroup sums a chunk's segments, bound by its own load rate, so more and
+// smaller chunks finish sooner), as long as every chunk's candidate list
+// still fits one merge workgroup (SEL_MERGE / K lists, K <= bmax).  Every
+// chunk holds at least one whole block, hence at least K rows.
+static int64_t sel_blocks_per_chunk(int64_t k, int64_t bmax, int64_t nseg) {
+    int64_t bpc = 4096 / bmax;
+    if (bpc > 256) bpc = 256;
+    if (bpc < 1) bpc = 1;
+    if (nseg > 2) {
+        const int64_t per = 8192 / bmax;
+        int64_t b2 = (8192 / nseg) / bmax;
+        const int64_t bmin = (k + per - 1) / per;
+        if (b2 < bmin) b2 = bmin;
+        if (b2 < 1) b2 = 1;
+        if (b2 < bpc) bpc = b2;
+    }
+    return bpc;
+}
+
 
 // Column chunking of the block step, the greedy Gram and the selection.
 void plan_layout(Layout &L, bool col) {
@@ -159,11 +180,8 @@ void plan_layout(Layout &L, bool col) {
         L.nch_g = 1;
         L.nseg = 1;
     }
-    int64_t bpc = 4096 / L.bmax;  // rows per chunk <= 4096, blocks per chunk <= 256
-    if (bpc > 256) bpc = 256;
-    if (bpc < 1) bpc = 1;
-    L.bpc = bpc;
-    L.nch_s = (int32_t)((L.k + bpc - 1) / bpc);
+    L.bpc = sel_blocks_per_chunk(L.k, L.bmax, L.nseg);
+    L.nch_s = (int32_t)((L.k + L.bpc - 1) / L.bpc);
 }
 
 void free_solve_buffers(rorbk_handle_s *h) {
@@ -1733,11 +1751,8 @@ extern "C" int ror_bk_residual_noalloc(const rorbk_matrix *A, int64_t block_rows
         return fail(RORBK_ERR_UNSUPPORTED, "blocks of %lld rows exceed the supported %d",
                     (long long)L.bmax, RORBK_MAX_BIG_BLOCK_ROWS);
     L.nseg = dense ? (int32_t)((L.n + 2047) / 2048) : 1;
-    int64_t bpc = 4096 / L.bmax;
-    if (bpc > 256) bpc = 256;
-    if (bpc < 1) bpc = 1;
-    L.bpc = bpc;
-    L.nch_s = (int32_t)((L.k + bpc - 1) / bpc);
+    L.bpc = sel_blocks_per_chunk(L.k, L.bmax, L.nseg);
+    L.nch_s = (int32_t)((L.k + L.bpc - 1) / L.bpc);
     // scratch layout: control block, counter, norm scratch | chunk norms |
     // block norms (unless the caller takes them) | partial products
     const size_t off_cn = 1024;
