@@ -20,7 +20,9 @@ namespace rorbk {
 // valid row: their products only reach outputs that are not written); the
 // last partial step takes the guarded loads.  acc is in the MFMA layout:
 // element (i, j) of sub-tile (s, t) in register i / 4 of lane (i % 4) 16 + j.
-template <typename T, bool AL>
+// U2: two macro steps of FP64 rows in flight (the contiguous rows of a block
+// Gram; measured faster there, slower on the gathered rows of a greedy Gram).
+template <typename T, bool AL, bool U2 = false>
 __device__ __forceinline__ void gram64_accumulate(const T *const (&pa)[4], const T *const (&pb)[4],
                                                   const bool (&va)[4], const bool (&vb)[4],
                                                   bool same, int64_t c0, int64_t c1,
@@ -28,7 +30,7 @@ __device__ __forceinline__ void gram64_accumulate(const T *const (&pa)[4], const
     constexpr int VW = Tr<T>::VW;
     constexpr int E = (sizeof(T) == 8) ? 4 : VW;   // columns per lane per macro step
     constexpr int NL = E / VW;                      // 16-byte loads per row per step
-    constexpr int U = (sizeof(T) == 8) ? 1 : 2;     // macro steps in flight
+    constexpr int U = (sizeof(T) == 8 && !U2) ? 1 : 2;   // macro steps in flight
     const int w = threadIdx.x >> 6, g = (threadIdx.x & 63) >> 4;
     const int64_t stepc = 4 * E;
     const int64_t span = ((c1 - c0 + 4 * stepc - 1) / (4 * stepc)) * stepc;

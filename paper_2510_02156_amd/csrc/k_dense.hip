@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) void k_block_gram64(const T *__restrict__ A, i
         pb[s2] = A + (r0 + (vb[s2] ? ib : 0)) * ld;
     }
     dvec4 acc[4][4];
-    gram64_accumulate<T, AL>(pa, pb, va, vb, bi == bj, 0, n, acc);
+    gram64_accumulate<T, AL, true>(pa, pb, va, vb, bi == bj, 0, n, acc);
     gram64_store(acc, bi, bj, bt, Gs + t * kpmax);
 }
 
