@@ -221,6 +221,35 @@ def test_multi_slab_update_workgroups(m, n, br, storage):
         assert e < 1e-4
 
 
+def test_selection_chunks_of_many_segments():
+    """n = 16385 columns (9 column segments of the residual pass): the
+    selection splits the 1200 rows into chunks of at most 8192 partial
+    products (906 and 294 rows, both shorter than a full set of rounds),
+    sums the 9 segments in groups of four loads and merges the two candidate
+    lists.  FP64 trajectory against the oracle (draws and greedy sets
+    bit-exact) and the top-K of given residuals bit-exact."""
+    rng = np.random.default_rng(7)
+    m, n, br, lam, iters = 1200, 16385, 6, 1e-3, 15
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    b = A @ rng.standard_normal(n)
+    ref = O.solve(A, br, lam, b, seed=5, max_iters=iters)
+    sol = P.Solver(dev(A), br, lam)
+    _, Wref = O.proposal(O.cosine_rowsums(A, br), n)
+    sol.set_proposal(Wref)
+    x, _ = sol.solve(dev(b), seed=5, tol=0.0, max_iters=iters, record=True)
+    rec = sol.record()
+    np.testing.assert_array_equal(rec["tau"], ref["tau"])
+    np.testing.assert_array_equal(rec["I"], ref["I"])
+    e = rel(host(x), ref["x"])
+    print(f"many-segment selection: rel err {e:.2e}", flush=True)
+    assert e < 1e-10
+    for trial in range(2):
+        r = rng.standard_normal(m) * 10.0 ** rng.uniform(-8, 0, m)
+        if trial == 1:   # ties
+            r = rng.choice([-2.0, 0.0, 1.0, 2.0], size=m)
+        np.testing.assert_array_equal(host(sol.topk(dev(r))), O.topk(r, sol.K))
+
+
 def test_stop_test_and_iteration_count():
     s = make(1000, 300, 1e4)
     ref = O.solve(s["A"], 20, 1e-3, s["b"], seed=9, tol=0.05, max_iters=500)
