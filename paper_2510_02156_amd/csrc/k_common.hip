@@ -193,9 +193,9 @@ __device__ __forceinline__ void block_minmax_u32(uint32_t mx, uint32_t mn, uint3
 // the top K (elements with a larger masked key are all in).  Stops as soon as
 // the boundary bucket holds exactly `need` elements.  One barrier per pass:
 // every wave reads the whole histogram and finds the boundary bin itself (the
-// same result in every wave), and the pass also clears the histogram of the
-// pass after next of three in rotation (the one every wave finished reading
-// before the previous pass's barrier).
+// same result in every wave), and each pass also clears the next pass's
+// histogram: three in rotation, so that one was last read two passes back,
+// which every wave finished before the previous pass's barrier.
 template <int PER>
 __device__ __forceinline__ void radix_select(const uint64_t (&kv)[PER], int N, int K, int shift,
                                              uint32_t vmax, uint32_t vmin, uint64_t *T_out,
